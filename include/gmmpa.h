@@ -1,0 +1,143 @@
+/*
+ * gmmpa.h - C ABI of the MI355X (gfx950) massively parallel GMMNLSE propagator.
+ *
+ * The library integrates the generalized multimode nonlinear Schroedinger
+ * equation, Eq. (1) of Wright et al., "Multimode Nonlinear Fiber Optics:
+ * Massively Parallel Numerical Solver, Tutorial and Outlook", with the
+ * massively parallel algorithm (MPA) of its Sec. III.D: change of variables
+ * Eq. (cov), integral form Eq. (MPA_eq), M small steps dz per large step
+ * L = M dz, integrands evaluated in parallel, trapezoid rule, fixed-point
+ * iteration until the relative change falls below a threshold.
+ *
+ * Conventions (all SI units):
+ *   t_k = (k - Nt/2) dt;  omega_k = 2 pi fftfreq(Nt, dt)[k];
+ *   a field is A(t) = sum_k A~(omega_k) exp(-i omega_k t), i.e. d/dt <-> -i omega;
+ *   D_omega = i (db0 + db1 omega + sum_{n>=2} beta_n omega^n / n!)   (Sec. III.D);
+ *   self-steepening factor (1 + omega/omega0)                      (Eq. (MPA_eq));
+ *   Raman convolution: circular over the window with weights h_R(k dt),
+ *   normalised to unit sum (zero-frequency gain 1).
+ *
+ * Fields cross the boundary as device buffers of interleaved complex numbers,
+ * mode-major: element (p, k) at index p*Nt + k.  The element type is complex
+ * double for GMM_FP64 plans and complex float for GMM_FP32 plans.
+ *
+ * Return codes: 0 success; GMM_NOT_CONVERGED (+1) the propagation completed
+ * but at least one large step stopped at max_iter without reaching tol (the
+ * output is valid, the statistics say which); negative values are errors and
+ * leave the output unspecified.  No call throws; gmm_last_error() gives a
+ * message for the last failure on the calling thread.
+ */
+#ifndef GMMPA_H
+#define GMMPA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMM_OK 0
+#define GMM_NOT_CONVERGED 1
+#define GMM_ERR_ARG (-1)         /* invalid argument (size, step, grid, null pointer) */
+#define GMM_ERR_NOMEM (-2)       /* device allocation failed */
+#define GMM_ERR_TENSOR (-3)      /* coupling tensor lacks the symmetry the packed path needs */
+#define GMM_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define GMM_ERR_UNSUPPORTED (-5) /* valid input outside what this build implements */
+#define GMM_ERR_DIVERGED (-6)    /* the iteration produced non-finite values */
+
+typedef struct gmm_plan_s* gmm_plan;
+
+typedef enum {
+  GMM_FP64 = 0,   /* complex128 fields, FP64 transforms, FP64 MFMA contraction */
+  GMM_FP32 = 1    /* complex64 fields, FP32 transforms, FP32 MFMA contraction */
+} gmm_precision;
+
+typedef struct {
+  int n_modes;          /* N >= 1 spatial modes */
+  int nt;               /* Nt time samples: a power of two, 2^8..2^15 (2^14 max for GMM_FP64) */
+  int n_beta;           /* columns of betas, >= 1 */
+  double dt;            /* time step (s) */
+  double omega0;        /* carrier angular frequency (rad/s) */
+  double n2;            /* nonlinear index (m^2/W) */
+  double fR;            /* Raman fraction, 0 <= fR <= 1 */
+  int self_steepening;  /* 1: keep (1 + (i/omega0) d/dt); 0: replace it by 1 */
+  int precision;        /* gmm_precision */
+  double tol;           /* threshold on ||psi^(n+1) - psi^(n)|| / ||psi^(n+1)|| (FP64) */
+  int max_iter;         /* iteration cap per large step (>= 1) */
+  int fixed_iters;      /* > 0: run exactly this many iterations per large step, ignore tol */
+} gmm_params;
+
+typedef struct {
+  int large_steps;       /* large steps taken */
+  int small_steps;       /* small steps dz covered (sum of M per large step) */
+  long long iterations;  /* total iterations over all large steps */
+  long long evaluations; /* nonlinear-operator evaluations (sub-step integrands) */
+  int max_iters_seen;    /* largest iteration count of one large step */
+  int nonconverged_steps;/* large steps that stopped at max_iter */
+  double last_eps;       /* relative change of the last iteration of the last large step */
+  double dz_used;        /* small step actually used (L is covered exactly) */
+  double energy_in, energy_out;   /* sum_p int |A_p|^2 dt at z = 0 and z = L (J), FP64 */
+  double photons_in, photons_out; /* sum_{p,k} |A~_p(w_k)|^2 / (w0 + w_k), FP64 (arbitrary units) */
+} gmm_stats;
+
+/*
+ * gmm_plan_create - validate and copy the inputs of Eq. (1), precompute what
+ * does not change along the fibre, and bind a HIP stream.
+ *   out    : receives the plan (owned by the caller until gmm_plan_destroy).
+ *   p      : parameters (copied).
+ *   betas  : host [N][n_beta] Taylor coefficients about omega0 (rad/m, s/m,
+ *            s^2/m, ...); columns 0 and 1 relative to the first mode
+ *            (paragraph after Eq. (1)).  Copied.
+ *   SK     : host [N^4] real coupling tensor S^K_plmn, index ((p*N+l)*N+m)*N+n,
+ *            in m^-2 (Eq. (2)).  It must satisfy S_plmn = S_plnm = S_lpmn
+ *            (true for Eq. (2)); otherwise GMM_ERR_TENSOR.  Copied.
+ *   SR     : host [N^4] Raman tensor, or NULL for S^R = S^K (Eq. (2) with real
+ *            scalar modes).  A non-NULL SR different from SK returns
+ *            GMM_ERR_UNSUPPORTED in this build.
+ *   hR     : host [Nt] samples h_R(k dt), k = 0..Nt-1 (1/s); required when
+ *            fR > 0, ignored otherwise.  Copied.
+ *   stream : hipStream_t on which all work of this plan is queued (NULL =
+ *            the null stream).  Borrowed, not owned.
+ * Allocates device memory for the constants; workspace is allocated by the
+ * first propagate and grown as needed.
+ */
+int gmm_plan_create(gmm_plan* out, const gmm_params* p, const double* betas, const double* SK,
+                    const double* SR, const double* hR, void* stream);
+
+/*
+ * gmm_propagate - propagate A0 over a fibre of length L with the MPA.
+ *   A0   : device [N][Nt] field at z = 0, time domain, sqrt(W).  Read only.
+ *   L    : fibre length (m) > 0.
+ *   dz   : requested small step (m) > 0; the step used is L/n with
+ *          n = round(L/dz) when L/dz is an integer to 1e-9, else ceil(L/dz).
+ *   M    : small steps per large step (>= 1); a last, shorter large step takes
+ *          the remaining n mod M small steps.
+ *   Aout : device [N][Nt] field at z = L (may alias A0).
+ *   st   : statistics (may be NULL).
+ * Work is queued on the plan's stream; the call returns after the result is
+ * complete (it reads the per-step convergence flag from the device).
+ * One propagate at a time per plan.
+ */
+int gmm_propagate(gmm_plan plan, const void* A0, double L, double dz, int M, void* Aout, gmm_stats* st);
+
+/*
+ * gmm_nonlinear - the integrand factor of Eq. (MPA_eq) for `count` fields:
+ *   out_c(w) = i (n2 w0/c) (1 + s w/w0) F{ sum_lmn [(1-fR) S_plmn A_l A_m A_n^*
+ *                                            + fR S_plmn A_l (h_R * A_m A_n^*)] }
+ *   At   : device [count][N][Nt] spectra A~ (FFT order).  Read only.
+ *   out  : device [count][N][Nt] (must not alias At).
+ * Queued on the plan's stream; returns without synchronising.
+ */
+int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out);
+
+/* Release every device buffer of the plan.  NULL is accepted. */
+int gmm_plan_destroy(gmm_plan plan);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* gmm_last_error(void);
+
+/* Device bytes currently held by the plan (constants + workspace). */
+long long gmm_plan_device_bytes(gmm_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMMPA_H */

@@ -1,0 +1,61 @@
+// Shared device-side types for the GMMNLSE propagation kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmm {
+
+// Control block of one large step, written by the norm kernel, read by the
+// guarded kernels of later (speculatively queued) iterations and by the host.
+struct Ctrl {
+  double eps;
+  int iters;
+  int done;    // 1: no more iterations (converged, fixed count reached, or failed)
+  int status;  // 0 ok, 1 max_iter reached without eps < tol, 2 non-finite eps
+  int pad;
+};
+
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+
+// exp(i*phase) with the phase first folded into [-pi, pi] in double precision,
+// then evaluated in the field precision T.
+template <typename T>
+__device__ __forceinline__ cplx<T> expi_reduced(double phase);
+template <>
+__device__ __forceinline__ cplx<double> expi_reduced<double>(double phase) {
+  const double twopi = 6.283185307179586476925286766559;
+  double r = phase - twopi * rint(phase * (1.0 / twopi));
+  double s, c;
+  sincos(r, &s, &c);
+  return {c, s};
+}
+template <>
+__device__ __forceinline__ cplx<float> expi_reduced<float>(double phase) {
+  const double twopi = 6.283185307179586476925286766559;
+  float r = (float)(phase - twopi * rint(phase * (1.0 / twopi)));
+  float s, c;
+  sincosf(r, &s, &c);
+  return {c, s};
+}
+
+// Angular frequency of spectral bin k on an nt-point grid: 2*pi*fftfreq(nt, dt).
+__device__ __forceinline__ double omega_of(int k, int nt, double domega) {
+  return (double)(k < nt / 2 ? k : k - nt) * domega;
+}
+
+}  // namespace gmm

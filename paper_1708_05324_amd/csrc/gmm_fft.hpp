@@ -1,0 +1,171 @@
+// Block-wide complex FFT for one row of length N = 2^LOGN (8 <= LOGN <= 15).
+//
+// Design (gfx950): one workgroup owns one row.  Each thread keeps R = 16 (or 32
+// for 2^15) points in registers, does a radix-R butterfly per pass entirely in
+// registers, and the passes exchange data through LDS in Stockham (self-
+// sorting) order, so no bit-reversal pass is ever needed.  Real and imaginary
+// parts travel through LDS separately (N scalars + 1/16 padding), which keeps
+// an FP64 2^14 row inside the 160 KB LDS and lets two FP32 rows share a CU.
+//
+// The pass schedule is [R, rem, R, ..., R]: first and last passes both have
+// radix R, so the register of the i-th point is i*THREADS + tid both on entry
+// and on exit.  Element-wise work before (phase factors, pair products) and
+// after (spectral filters, shock factor) is done in registers on that layout,
+// and a forward transform can feed an inverse one without touching LDS.
+//
+// SIGN = -1:  X_k = sum_j x_j exp(-2 pi i jk/N)   (numpy fft)
+// SIGN = +1:  X_k = sum_j x_j exp(+2 pi i jk/N)   (numpy ifft times N)
+#pragma once
+#include "gmm_common.hpp"
+
+namespace gmm {
+
+template <int LOGN_>
+struct FftShape {
+  static constexpr int LOGN = LOGN_;
+  static constexpr int N = 1 << LOGN;
+  static constexpr int LOGR = (LOGN >= 15) ? 5 : 4;
+  static constexpr int R = 1 << LOGR;
+  static constexpr int THREADS = N / R;
+  static constexpr int NFULL = LOGN / LOGR;
+  static constexpr int REM = LOGN % LOGR;
+  static constexpr int NPASS = NFULL + (REM ? 1 : 0);
+  static constexpr int LDS_ELEMS = N + (N >> 4);  // one padding slot per 16
+  static constexpr int logp(int i) { return (i == 1 && REM) ? REM : LOGR; }
+  static constexpr int log_stride(int i) {
+    int s = 0;
+    for (int k = 0; k < i; ++k) s += logp(k);
+    return s;
+  }
+  static_assert(LOGN >= 8 && LOGN <= 15, "row length must be 2^8 .. 2^15");
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// cos/sin of 2*pi*m/32, m = 0..31, from the first-octant table by symmetry.
+__device__ __forceinline__ constexpr double c32_table(int r) {
+  return r == 0 ? 1.0
+       : r == 1 ? 0.98078528040323043
+       : r == 2 ? 0.92387953251128674
+       : r == 3 ? 0.83146961230254524
+       : r == 4 ? 0.70710678118654752
+       : r == 5 ? 0.55557023301960218
+       : r == 6 ? 0.38268343236508977
+       : r == 7 ? 0.19509032201612826
+       : 0.0;
+}
+
+template <typename T, int SIGN>
+__device__ __forceinline__ cplx<T> root32(int m) {  // exp(SIGN * 2 pi i m / 32)
+  int q = (m >> 3) & 3, r = m & 7;
+  double c, s;
+  if (q == 0) { c = c32_table(r); s = c32_table(8 - r); }
+  else if (q == 1) { c = -c32_table(8 - r); s = c32_table(r); }
+  else if (q == 2) { c = -c32_table(r); s = -c32_table(8 - r); }
+  else { c = c32_table(8 - r); s = -c32_table(r); }
+  return {(T)c, (T)(SIGN * s)};
+}
+
+// In-register DFT of P points (natural order in and out), decimation in
+// frequency with compile-time twiddles; the final bit reversal is a register
+// renaming once unrolled.
+template <typename T, int P, int SIGN>
+__device__ __forceinline__ void dft_reg(cplx<T>* u) {
+#pragma unroll
+  for (int span = P / 2; span >= 1; span >>= 1) {
+#pragma unroll
+    for (int start = 0; start < P; start += 2 * span) {
+#pragma unroll
+      for (int k = 0; k < span; ++k) {
+        cplx<T> a = u[start + k], b = u[start + k + span];
+        u[start + k] = cadd(a, b);
+        cplx<T> d = csub(a, b);
+        const int m = k * (P / (2 * span));  // twiddle exponent in units of 1/P
+        if (m == 0) {
+          u[start + k + span] = d;
+        } else if (4 * m == P) {  // exp(SIGN*i*pi/2) = SIGN*i
+          u[start + k + span] = SIGN > 0 ? cplx<T>{-d.im, d.re} : cplx<T>{d.im, -d.re};
+        } else {
+          u[start + k + span] = cmul(d, root32<T, SIGN>(m * (32 / P)));
+        }
+      }
+    }
+  }
+  cplx<T> tmp[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) tmp[i] = u[i];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0, x = i; (1 << b) < P; ++b, x >>= 1) r = (r << 1) | (x & 1);
+    u[r] = tmp[i];
+  }
+}
+
+// One Stockham pass: butterflies read at j + q*N/P, write at
+// (j / Ns) * Ns * P + j % Ns + q * Ns, with twiddles exp(SIGN 2 pi i q (j % Ns) / (Ns P)).
+template <class S, int I, typename T, int SIGN>
+__device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], int tid, const cplx<T>* __restrict__ tw) {
+  constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
+  constexpr int LNS = S::log_stride(I), NS = 1 << LNS;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = tid + b * S::THREADS;
+    if constexpr (NS > 1) {
+      const int k = j & (NS - 1);
+#pragma unroll
+      for (int q = 1; q < P; ++q) {
+        cplx<T> w = tw[(q * k) << (S::LOGN - LNS - LP)];  // table holds exp(-2 pi i m / N)
+        if (SIGN > 0) w.im = -w.im;
+        v[b * P + q] = cmul(v[b * P + q], w);
+      }
+    }
+    dft_reg<T, P, SIGN>(&v[b * P]);
+  }
+}
+
+// Write pass I's outputs to LDS (one component), read pass I+1's inputs.
+template <class S, int I, typename T, bool IMAG>
+__device__ __forceinline__ void fft_exchange_component(cplx<T> (&v)[S::R], T* lds, int tid) {
+  constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
+  constexpr int LNS = S::log_stride(I), NS = 1 << LNS;
+  constexpr int LP2 = S::logp(I + 1), P2 = 1 << LP2, B2 = S::R / P2;
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = tid + b * S::THREADS;
+    const int base = ((j >> LNS) << (LNS + LP)) + (j & (NS - 1));
+#pragma unroll
+    for (int q = 0; q < P; ++q) lds[lds_pad(base + (q << LNS))] = IMAG ? v[b * P + q].im : v[b * P + q].re;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B2; ++b) {
+    const int j = tid + b * S::THREADS;
+#pragma unroll
+    for (int q = 0; q < P2; ++q) {
+      T x = lds[lds_pad(j + q * (S::N / P2))];
+      if (IMAG) v[b * P2 + q].im = x; else v[b * P2 + q].re = x;
+    }
+  }
+}
+
+template <class S, int I, typename T, int SIGN>
+__device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw) {
+  fft_pass_compute<S, I, T, SIGN>(v, tid, tw);
+  if constexpr (I + 1 < S::NPASS) {
+    fft_exchange_component<S, I, T, false>(v, lds, tid);
+    fft_exchange_component<S, I, T, true>(v, lds, tid);
+    fft_passes<S, I + 1, T, SIGN>(v, lds, tid, tw);
+  }
+}
+
+// Full transform of the row held in v (v[i] = x[tid + i*THREADS]) in place.
+// `lds` must hold S::LDS_ELEMS scalars of type T.  All threads must call it.
+template <class S, typename T, int SIGN>
+__device__ __forceinline__ void block_fft(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw) {
+  fft_passes<S, 0, T, SIGN>(v, lds, tid, tw);
+}
+
+}  // namespace gmm

@@ -1,0 +1,385 @@
+// Device kernels of one MPA nonlinear evaluation and of the trapezoid iteration
+// (Sec. III.D of Wright et al.: change of variables Eq. (cov), integral form
+// Eq. (MPA_eq), trapezoid rule over M small steps, iteration to a threshold).
+//
+// Layouts in HBM (all row-major, time or frequency index contiguous):
+//   psi, I, work : [count][N][Nt] complex   (mode-major rows of Nt points)
+//   Bp            : [count][Np][Nt] real     (one row per mode pair m <= n)
+//   ST            : [Rpad][Rpad] real        (packed coupling matrix, transposed)
+// Spectra are in FFT order (bin k <-> omega = 2 pi fftfreq(Nt, dt)[k]); a field
+// is A(t) = sum_k A~_k exp(-i w_k t), so the spectrum is (1/Nt) * FFT_{+}(A)
+// and the field is FFT_{-}(A~).
+#pragma once
+#include "gmm_fft.hpp"
+
+namespace gmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bool skip_iteration(const Ctrl* c) {
+  return c != nullptr && *(volatile const int*)&c->done != 0;
+}
+
+// Dispersion phase beta(omega) - beta0 of mode p: sum_n coef[n] omega^n with
+// coef[n] = beta_n / n! (Horner, FP64).  D_omega = i * this.
+__device__ __forceinline__ double disp_phase(const double* __restrict__ coef, int nb, double w) {
+  double acc = 0.0;
+  for (int n = nb - 1; n >= 0; --n) acc = acc * w + coef[n];
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Plain row transform: out = scale * FFT_SIGN(in), one row per block.
+template <typename T, int LOGN, int SIGN>
+__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_fft_rows(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, T scale, const cplx<T>* __restrict__ tw) {
+  using S = FftShape<LOGN>;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const size_t row = (size_t)blockIdx.x * S::N;
+  cplx<T> v[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) v[i] = in[row + tid + i * S::THREADS];
+  block_fft<S, T, SIGN>(v, lds, tid, tw);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) out[row + tid + i * S::THREADS] = cscale(v[i], scale);
+}
+
+// ---------------------------------------------------------------------------
+// a1: A_j(t) = FFT_{-}[ exp(D_w z_j) psi_j ],  z_j = (j0 + jj) * dz.
+// grid (N, count); psi row (jj, p) at psi + (jj * psi_jrows + p) * Nt, where
+// psi_jrows is a row count: N for one field per sub-step, 0 to reuse psi_0.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_phase_to_time(
+    const cplx<T>* __restrict__ psi, long psi_jrows, cplx<T>* __restrict__ A, const double* __restrict__ coef,
+    int nb, int j0, double dz, double domega, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
+  const cplx<T>* src = psi + ((size_t)jj * psi_jrows + p) * S::N;
+  const double z = (double)(j0 + jj) * dz;
+  const double* cp = coef + p * nb;
+  cplx<T> v[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int k = tid + i * S::THREADS;
+    cplx<T> e = expi_reduced<T>(disp_phase(cp, nb, omega_of(k, S::N, domega)) * z);
+    v[i] = cmul(src[k], e);
+  }
+  block_fft<S, T, -1>(v, lds, tid, tw);
+  cplx<T>* dst = A + ((size_t)jj * N + p) * S::N;
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) dst[tid + i * S::THREADS] = v[i];
+}
+
+// ---------------------------------------------------------------------------
+// a2 + a3: pair products and Raman convolution.  For pairs Q = (m, n), m <= n:
+//   B_Q(t)  = Re(A_m A_n^*)
+//   B'_Q(t) = (1 - fR) B_Q + fR (h_R * B_Q)(t)
+// Two real rows travel as one complex row z = B_Q1 + i B_Q2; h_R is real, so
+// FFT_{-}(Hs * FFT_{+}(z)) = (h*B_Q1) + i (h*B_Q2) exactly.  Hs = H / Nt.
+// grid (ceil(Np / 2), count).
+template <typename T, int LOGN, bool RAMAN>
+__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_pairs(
+    const cplx<T>* __restrict__ A, T* __restrict__ Bp, const int2* __restrict__ pairs, int N, int Np, T wk, T wr,
+    const cplx<T>* __restrict__ Hs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
+  const int tid = threadIdx.x, jj = blockIdx.y;
+  const int Q1 = 2 * blockIdx.x, Q2 = Q1 + 1;
+  const bool has2 = Q2 < Np;
+  const int2 a = pairs[Q1];
+  const int2 b = has2 ? pairs[Q2] : a;
+  const cplx<T>* Aj = A + (size_t)jj * N * S::N;
+  const cplx<T>* am = Aj + (size_t)a.x * S::N;
+  const cplx<T>* an = Aj + (size_t)a.y * S::N;
+  const cplx<T>* bm = Aj + (size_t)b.x * S::N;
+  const cplx<T>* bn = Aj + (size_t)b.y * S::N;
+  cplx<T> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    cplx<T> x = am[t], y = an[t];
+    T b1 = x.re * y.re + x.im * y.im;
+    T b2 = 0;
+    if (has2) {
+      cplx<T> u = bm[t], w = bn[t];
+      b2 = u.re * w.re + u.im * w.im;
+    }
+    z[i] = {b1, b2};
+  }
+  T* o1 = Bp + ((size_t)jj * Np + Q1) * S::N;
+  T* o2 = o1 + S::N;
+  if constexpr (RAMAN) {
+    cplx<T> z0[S::R];
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) z0[i] = z[i];
+    block_fft<S, T, +1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Hs[tid + i * S::THREADS]);
+    block_fft<S, T, -1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) {
+      const int t = tid + i * S::THREADS;
+      o1[t] = wk * z0[i].re + wr * z[i].re;
+      if (has2) o2[t] = wk * z0[i].im + wr * z[i].im;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) {
+      const int t = tid + i * S::THREADS;
+      o1[t] = z[i].re;
+      if (has2) o2[t] = z[i].im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a5: C_r(t) = sum_Q S^_rQ B'_Q(t) on MFMA, then NL_p(t) = sum_l C_{(p,l)}(t) A_l(t).
+// One block = one 64-column time tile of one sub-step, all Rpad = 64*RT rows;
+// wave w owns rows [16 RT w, 16 RT (w+1)).  NL overwrites A in place (every
+// wave reads all the A values of its tile before anyone writes).
+template <typename T>
+struct Mfma;
+// 16x16x4 tiles: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+// Accumulator register i of lane l holds D[row][l % 16] with
+//   FP32: row = 4 (l / 16) + i        FP64: row = (l / 16) + 4 i
+// (the FP64 layout interleaves rows; both measured with a one-hot probe).
+template <>
+struct Mfma<float> {
+  typedef floatx4 acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lgrp, int i) { return 4 * lgrp + i; }
+};
+template <>
+struct Mfma<double> {
+  typedef doublex4 acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int lgrp, int i) { return lgrp + 4 * i; }
+};
+
+template <int RT>
+struct ContractShape {
+  static constexpr int RPAD = 64 * RT;
+  static constexpr int TN = 64;
+  static constexpr int KC = 16;
+  static constexpr int NMAX = RT == 1 ? 10 : RT == 2 ? 15 : RT == 3 ? 19 : 22;
+  template <typename T>
+  static constexpr size_t lds_bytes() {
+    size_t a = (size_t)(KC * RPAD + KC * TN) * sizeof(T);
+    size_t c = (size_t)RPAD * TN * sizeof(T);
+    return a > c ? a : c;
+  }
+};
+
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void k_contract(
+    const T* __restrict__ ST, const T* __restrict__ Bp, cplx<T>* A_NL, const int* __restrict__ pidx, int N,
+    int Np, int Nt, const Ctrl* ctrl) {
+  using CS = ContractShape<RT>;
+  constexpr int RPAD = CS::RPAD, TN = CS::TN, KC = CS::KC;
+  typedef typename Mfma<T>::acc_t acc_t;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sA = reinterpret_cast<T*>(smem_raw);  // [KC][RPAD]
+  T* sB = sA + KC * RPAD;                  // [KC][TN]
+  T* sC = reinterpret_cast<T*>(smem_raw);  // [RPAD][TN] after the K loop
+  const int tiles = Nt / TN;
+  const int jj = blockIdx.x / tiles, t0 = (blockIdx.x - jj * tiles) * TN;
+  const T* Bj = Bp + (size_t)jj * Np * Nt;
+  cplx<T>* Aj = A_NL + (size_t)jj * N * Nt;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  acc_t acc[RT][4];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < RPAD; k0 += KC) {
+    for (int i = tid; i < KC * RPAD; i += 256) sA[i] = ST[(size_t)k0 * RPAD + i];
+    for (int i = tid; i < KC * TN; i += 256) {
+      const int k = i / TN, c = i - k * TN, Q = k0 + k;
+      sB[i] = Q < Np ? Bj[(size_t)Q * Nt + t0 + c] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T b[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = sB[(kk + lk) * TN + c * 16 + lr];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const T a = sA[(kk + lk) * RPAD + wave * 16 * RT + r * 16 + lr];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = Mfma<T>::mma(a, b[c], acc[r][c]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wave * 16 * RT + r * 16 + Mfma<T>::out_row(lk, i);
+        sC[row * TN + c * 16 + lr] = acc[r][c][i];
+      }
+  __syncthreads();
+  // epilogue: lane = column, wave-uniform modes p = wave, wave + 4, ...
+  cplx<T> a[CS::NMAX];
+#pragma unroll
+  for (int l = 0; l < CS::NMAX; ++l)
+    if (l < N) a[l] = Aj[(size_t)l * Nt + t0 + lane];
+  __syncthreads();
+  for (int p = wave; p < N; p += 4) {
+    cplx<T> s = {0, 0};
+#pragma unroll
+    for (int l = 0; l < CS::NMAX; ++l)
+      if (l < N) {
+        const T c = sC[pidx[p * N + l] * TN + lane];
+        s.re += c * a[l].re;
+        s.im += c * a[l].im;
+      }
+    Aj[(size_t)p * Nt + t0 + lane] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a6: I_j(w) = exp(-D_w z_j) * i gamma^ (1 + s w/w0) * F{NL_j}(w),
+// F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt.  grid (N, count); in may alias out.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_spectral_out(
+    const cplx<T>* in, cplx<T>* out, const double* __restrict__ coef, int nb, int j0, double dz, double domega,
+    double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
+  const size_t row = ((size_t)jj * N + p) * S::N;
+  cplx<T> v[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) v[i] = in[row + tid + i * S::THREADS];
+  block_fft<S, T, +1>(v, lds, tid, tw);
+  const double z = (double)(j0 + jj) * dz;
+  const double* cp = coef + p * nb;
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int k = tid + i * S::THREADS;
+    const double w = omega_of(k, S::N, domega);
+    const T f = (T)(gscale * (shock ? 1.0 + w * inv_omega0 : 1.0));
+    cplx<T> e = expi_reduced<T>(-disp_phase(cp, nb, w) * z);
+    cplx<T> x = cmul(v[i], e);
+    out[row + k] = cplx<T>{-f * x.im, f * x.re};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a7 + a8: cumulative trapezoid and the relative change of psi (FP64 sums).
+//   psi_j^(n+1) = psi_0 + dz [ I_0/2 + sum_{k<j} I_k + I_j/2 ],  j = 1..M
+// first != 0: the previous iterate is psi_0 for every j (the initial guess).
+template <typename T>
+__global__ __launch_bounds__(256) void k_trapz(
+    const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
+    cplx<T>* __restrict__ psi, int first, int M, long nn, T dz, double* __restrict__ partials, const Ctrl* ctrl) {
+  if (skip_iteration(ctrl)) return;
+  __shared__ double red[2][256];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0, s = 0.0;
+  if (e < nn) {
+    const cplx<T> p0 = psi0[e];
+    const cplx<T> h0 = cscale(I0[e], T(0.5));
+    cplx<T> run = {0, 0};
+    for (int j = 0; j < M; ++j) {
+      const cplx<T> ij = I[(size_t)j * nn + e];
+      cplx<T> acc = cadd(cadd(h0, run), cscale(ij, T(0.5)));
+      cplx<T> nw = {p0.re + dz * acc.re, p0.im + dz * acc.im};
+      run = cadd(run, ij);
+      const cplx<T> old = first ? p0 : psi[(size_t)j * nn + e];
+      const double dr = (double)nw.re - (double)old.re, di = (double)nw.im - (double)old.im;
+      d += dr * dr + di * di;
+      s += (double)nw.re * nw.re + (double)nw.im * nw.im;
+      psi[(size_t)j * nn + e] = nw;
+    }
+  }
+  red[0][threadIdx.x] = d;
+  red[1][threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = red[0][0];
+    partials[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// a9: psi0 <- exp(D_w z) * src (element-wise over [N][Nt]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
+                                                const double* __restrict__ coef, int nb, int nt, long nn, double z,
+                                                double domega) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nn) return;
+  const int p = (int)(e / nt), k = (int)(e - (long)p * nt);
+  const cplx<T> x = src[e];
+  dst[e] = cmul(x, expi_reduced<T>(disp_phase(coef + p * nb, nb, omega_of(k, nt, domega)) * z));
+}
+
+// FP64 spectral sums for the bookkeeping: sum |A~|^2 and sum |A~|^2 / (w0 + w).
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_sums(const cplx<T>* __restrict__ At, int nt, long nn, double domega,
+                                                    double omega0, double* __restrict__ partials) {
+  __shared__ double red[2][256];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (e < nn) {
+    const int k = (int)(e % nt);
+    const cplx<T> x = At[e];
+    const double m = (double)x.re * x.re + (double)x.im * x.im;
+    a = m;
+    b = m / (omega0 + omega_of(k, nt, domega));
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = red[0][0];
+    partials[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// Raman spectral response: Hs[k] = H[k] / H[0] / Nt from H = FFT_{+}(normalised samples).
+template <typename T>
+__global__ __launch_bounds__(256) void k_finish_H(const cplx<double>* __restrict__ H, cplx<T>* __restrict__ Hs,
+                                                  int nt) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= nt) return;
+  const cplx<double> h0 = H[0];
+  const double den = h0.re * h0.re + h0.im * h0.im;
+  const cplx<double> x = H[k];
+  const double re = (x.re * h0.re + x.im * h0.im) / den, im = (x.im * h0.re - x.re * h0.im) / den;
+  Hs[k] = cplx<T>{(T)(re / nt), (T)(im / nt)};
+}
+
+}  // namespace gmm

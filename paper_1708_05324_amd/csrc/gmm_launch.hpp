@@ -1,0 +1,44 @@
+// Host-side launchers of the propagation kernels, one explicit instantiation
+// per field precision (gmm_kern_f32.hip, gmm_kern_f64.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gmm {
+
+template <typename T>
+struct cplx;
+struct Ctrl;
+
+template <typename T>
+struct Launch {
+  static bool supports_logn(int logn);
+  static hipError_t fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* out, T scale, int rows,
+                             const cplx<T>* tw, hipStream_t s);
+  static hipError_t phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const double* coef,
+                                  int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
+                                  const Ctrl* ctrl, hipStream_t s);
+  static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
+                          int count, T wk, T wr, const cplx<T>* Hs, const cplx<T>* tw, const Ctrl* ctrl,
+                          hipStream_t s);
+  static hipError_t contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
+                             int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
+                                 int count, int j0, double dz, double domega, double gscale, double inv_omega0,
+                                 int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, int first, int M,
+                          long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const double* coef, int nb, int nt, long nn, double z,
+                          double domega, hipStream_t s);
+  static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
+                              hipStream_t s);
+  static hipError_t finish_H(const cplx<double>* H, cplx<T>* Hs, int nt, hipStream_t s);
+};
+
+hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
+                             int max_iter, hipStream_t s);
+hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+
+inline int contract_max_rows() { return 256; }
+inline int trapz_blocks(long nn) { return (int)((nn + 255) / 256); }
+
+}  // namespace gmm

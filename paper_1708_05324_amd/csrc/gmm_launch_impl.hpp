@@ -1,0 +1,145 @@
+// Definitions of the Launch<T> members; included once per precision.
+#pragma once
+#include "gmm_kernels.hpp"
+#include "gmm_launch.hpp"
+
+namespace gmm {
+
+template <typename T>
+constexpr int max_logn() { return sizeof(T) == 8 ? 14 : 15; }
+
+#define GMM_LOGN_SWITCH(logn, BODY)                   \
+  switch (logn) {                                     \
+    case 8: { constexpr int LOGN = 8; BODY; } break;   \
+    case 9: { constexpr int LOGN = 9; BODY; } break;   \
+    case 10: { constexpr int LOGN = 10; BODY; } break; \
+    case 11: { constexpr int LOGN = 11; BODY; } break; \
+    case 12: { constexpr int LOGN = 12; BODY; } break; \
+    case 13: { constexpr int LOGN = 13; BODY; } break; \
+    case 14: { constexpr int LOGN = 14; BODY; } break; \
+    case 15: {                                         \
+      if constexpr (max_logn<T>() >= 15) {             \
+        constexpr int LOGN = max_logn<T>();            \
+        BODY;                                          \
+      } else {                                         \
+        return hipErrorInvalidValue;                   \
+      }                                                \
+    } break;                                           \
+    default: return hipErrorInvalidValue;              \
+  }
+
+template <typename T>
+bool Launch<T>::supports_logn(int logn) {
+  return logn >= 8 && logn <= max_logn<T>();
+}
+
+template <typename T>
+hipError_t Launch<T>::fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* out, T scale, int rows,
+                               const cplx<T>* tw, hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN>;
+    if (sign < 0)
+      hipLaunchKernelGGL((k_fft_rows<T, LOGN, -1>), dim3(rows), dim3(S::THREADS), 0, s, in, out, scale, tw);
+    else
+      hipLaunchKernelGGL((k_fft_rows<T, LOGN, +1>), dim3(rows), dim3(S::THREADS), 0, s, in, out, scale, tw);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const double* coef,
+                                    int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
+                                    const Ctrl* ctrl, hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN>;
+    hipLaunchKernelGGL((k_phase_to_time<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, psi, psi_jrows, A,
+                       coef, nb, j0, dz, domega, tw, ctrl);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
+                            int count, T wk, T wr, const cplx<T>* Hs, const cplx<T>* tw, const Ctrl* ctrl,
+                            hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN>;
+    dim3 grid((Np + 1) / 2, count);
+    if (raman)
+      hipLaunchKernelGGL((k_pairs<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, wk, wr, Hs,
+                         tw, ctrl);
+    else
+      hipLaunchKernelGGL((k_pairs<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, wk, wr, Hs,
+                         tw, ctrl);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
+                               int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+  dim3 grid(count * (Nt / 64));
+  switch (rt) {
+#define GMM_RT_CASE(R)                                                                                         \
+  case R: {                                                                                                    \
+    constexpr size_t lds = ContractShape<R>::template lds_bytes<T>();                                          \
+    if constexpr (lds > 65536) {                                                                               \
+      static const hipError_t attr = hipFuncSetAttribute((const void*)k_contract<T, R>,                        \
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (attr != hipSuccess) return attr;                                                                     \
+    }                                                                                                          \
+    hipLaunchKernelGGL((k_contract<T, R>), grid, dim3(256), lds, s, ST, Bp, A_NL, pidx, N, Np, Nt, ctrl);      \
+  } break;
+    GMM_RT_CASE(1)
+    GMM_RT_CASE(2)
+    GMM_RT_CASE(3)
+    GMM_RT_CASE(4)
+#undef GMM_RT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
+                                   int count, int j0, double dz, double domega, double gscale, double inv_omega0,
+                                   int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN>;
+    hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, coef, nb, j0,
+                       dz, domega, gscale, inv_omega0, shock, tw, ctrl);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, int first,
+                            int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, first, M, nn, dz,
+                     partials, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const double* coef, int nb, int nt, long nn, double z,
+                            double domega, hipStream_t s) {
+  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, coef, nb, nt, nn, z, domega);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
+                                hipStream_t s) {
+  hipLaunchKernelGGL((k_spec_sums<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, At, nt, nn, domega, omega0,
+                     partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::finish_H(const cplx<double>* H, cplx<T>* Hs, int nt, hipStream_t s) {
+  hipLaunchKernelGGL((k_finish_H<T>), dim3((nt + 255) / 256), dim3(256), 0, s, H, Hs, nt);
+  return hipGetLastError();
+}
+
+}  // namespace gmm

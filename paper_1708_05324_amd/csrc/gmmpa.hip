@@ -1,0 +1,487 @@
+// Host driver and C ABI of the massively parallel GMMNLSE propagator
+// (Sec. III.D of Wright et al.).  Everything numerical runs in the kernels of
+// gmm_kernels.hpp; this file validates inputs, precomputes per-plan constants
+// in FP64, owns device memory, and sequences the kernels of each large step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gmmpa.h"
+#include "gmm_common.hpp"
+#include "gmm_launch.hpp"
+
+using gmm::cplx;
+using gmm::Ctrl;
+using gmm::Launch;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define GMM_HIP(call)                                                                                \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess) return fail(GMM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+
+// Host FP64 radix-2 transform, used once per plan for the Raman response:
+// X_k = sum_j x_j exp(+2 pi i j k / n).
+void host_fft_plus(std::vector<std::complex<double>>& a) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t i = 0; i < n; i += len)
+      for (size_t k = 0; k < len / 2; ++k) {
+        const double ang = 2.0 * kPi * (double)k / (double)len;
+        const std::complex<double> w(std::cos(ang), std::sin(ang));
+        std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
+}  // namespace
+
+struct gmm_plan_s {
+  gmm_params prm{};
+  int N = 0, nt = 0, logn = 0, nb = 0, Np = 0, rt = 0, rpad = 0;
+  hipStream_t stream = nullptr;
+  double domega = 0, gamma_hat = 0;
+  bool fp64 = true, raman = false;
+  size_t esz = 0;  // bytes per real of the field precision
+  // constants
+  double* coef = nullptr;  // [N][nb] beta_n / n!
+  void* tw = nullptr;      // [nt] exp(-2 pi i m/nt) in field precision
+  void* Hs = nullptr;      // [nt] H / H0 / nt (Raman)
+  void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed
+  int* pidx = nullptr;     // [N][N]
+  int2* pairs = nullptr;   // [Np]
+  // workspace
+  int cap = 0;  // sub-step capacity
+  void *psi0 = nullptr, *I0 = nullptr, *psi = nullptr, *work = nullptr, *Bp = nullptr;
+  double* partials = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* h_ctrl = nullptr;         // pinned
+  double* h_partials = nullptr;   // pinned
+  long long const_bytes = 0, ws_bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(long long* counter, T** ptr, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GMM_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  *ptr = (T*)p;
+  *counter += (long long)bytes;
+  return GMM_OK;
+}
+
+void free_workspace(gmm_plan_s* P) {
+  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (P->partials) (void)hipFree(P->partials);
+  P->partials = nullptr;
+  P->cap = 0;
+  P->ws_bytes = 0;
+}
+
+size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->esz; }
+
+int ensure_workspace(gmm_plan_s* P, int cap) {
+  if (cap <= P->cap) return GMM_OK;
+  const size_t fb = field_bytes(P);
+  free_workspace(P);
+  long long* c = &P->ws_bytes;
+  int rc;
+  if ((rc = dev_alloc(c, &P->psi0, fb)) || (rc = dev_alloc(c, &P->I0, fb)) || (rc = dev_alloc(c, &P->psi, fb * cap)) ||
+      (rc = dev_alloc(c, &P->work, fb * cap)) ||
+      (rc = dev_alloc(c, &P->Bp, (size_t)cap * P->Np * P->nt * P->esz)) ||
+      (rc = dev_alloc(c, &P->partials, 2 * sizeof(double) * gmm::trapz_blocks((long)P->N * P->nt)))) {
+    free_workspace(P);
+    return rc;
+  }
+  P->cap = cap;
+  return GMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Typed sequencing of one nonlinear evaluation and one iteration.
+template <typename T>
+struct Runner {
+  gmm_plan_s* P;
+  const cplx<T>* tw() const { return (const cplx<T>*)P->tw; }
+
+  // out[c] = N~[ exp(D z_{j0+c}) psi_c ] * exp(-D z_{j0+c}) for c < count.
+  // psi_c starts at psi + c * jrows * Nt: jrows = N (one field per sub-step)
+  // or 0 (every sub-step reads the same field).  Field rows go through
+  // `work`; `out` may be `work` itself.
+  int eval(const cplx<T>* psi, long jrows, int count, int j0, double dz, cplx<T>* out, const Ctrl* ctrl) {
+    if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
+    if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
+    cplx<T>* W = (cplx<T>*)P->work;
+    GMM_HIP(Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
+                                     tw(), ctrl, P->stream));
+    GMM_HIP(Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
+                             (T)(1.0 - P->prm.fR), (T)P->prm.fR, (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
+    GMM_HIP(Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N, P->Np, P->nt, count, ctrl,
+                                P->stream));
+    GMM_HIP(Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
+                                    P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), ctrl,
+                                    P->stream));
+    return GMM_OK;
+  }
+
+  int iteration(int m, double dz, bool first) {
+    const long nn = (long)P->N * P->nt;
+    const cplx<T>* src = first ? (const cplx<T>*)P->psi0 : (const cplx<T>*)P->psi;
+    int rc = eval(src, first ? 0 : P->N, m, 1, dz, (cplx<T>*)P->work, P->ctrl);
+    if (rc) return rc;
+    GMM_HIP(Launch<T>::trapz((const cplx<T>*)P->psi0, (const cplx<T>*)P->I0, (const cplx<T>*)P->work,
+                             (cplx<T>*)P->psi, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl, P->stream));
+    GMM_HIP(gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol, P->prm.fixed_iters,
+                                   P->prm.max_iter, P->stream));
+    return GMM_OK;
+  }
+
+  int spec_sums(const cplx<T>* At, double* energy, double* photons) {
+    const long nn = (long)P->N * P->nt;
+    const int nblk = gmm::trapz_blocks(nn);
+    GMM_HIP(Launch<T>::spec_sums(At, P->nt, nn, P->domega, P->prm.omega0, P->partials, P->stream));
+    GMM_HIP(hipMemcpyAsync(P->h_partials, P->partials, 2 * sizeof(double) * nblk, hipMemcpyDeviceToHost,
+                           P->stream));
+    GMM_HIP(hipStreamSynchronize(P->stream));
+    double a = 0, b = 0;
+    for (int i = 0; i < nblk; ++i) {
+      a += P->h_partials[2 * i];
+      b += P->h_partials[2 * i + 1];
+    }
+    *energy = a * P->nt * P->prm.dt;  // Parseval: sum_t |A|^2 = Nt sum_k |A~|^2
+    *photons = b;
+    return GMM_OK;
+  }
+
+  int propagate(const void* A0, double L, double dz_req, int M, void* Aout, gmm_stats* st) {
+    const long nn = (long)P->N * P->nt;
+    // small steps: cover L exactly
+    const double r = L / dz_req;
+    long n_small = (std::fabs(r - std::round(r)) < 1e-9 * std::max(1.0, r)) ? (long)std::llround(r)
+                                                                            : (long)std::ceil(r);
+    if (n_small < 1) n_small = 1;
+    const double dz = L / (double)n_small;
+    int rc = ensure_workspace(P, M);
+    if (rc) return rc;
+    gmm_stats s{};
+    s.dz_used = dz;
+    // A~(0) = (1/Nt) FFT_{+}(A0)
+    GMM_HIP(Launch<T>::fft_rows(P->logn, +1, (const cplx<T>*)A0, (cplx<T>*)P->psi0, (T)(1.0 / P->nt), P->N, tw(),
+                                P->stream));
+    if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_in, &s.photons_in))) return rc;
+    long done = 0;
+    int status = GMM_OK;
+    while (done < n_small) {
+      const int m = (int)std::min<long>(M, n_small - done);
+      GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));
+      // I_0 = N~[A(z0)] (no phase: z = 0), unguarded
+      if ((rc = eval((const cplx<T>*)P->psi0, 0, 1, 0, dz, (cplx<T>*)P->I0, nullptr))) return rc;
+      int n_enq = 0;
+      if (P->prm.fixed_iters > 0) {
+        for (; n_enq < P->prm.fixed_iters; ++n_enq)
+          if ((rc = iteration(m, dz, n_enq == 0))) return rc;
+        GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
+        GMM_HIP(hipStreamSynchronize(P->stream));
+      } else {
+        // Queue two iterations, then keep one speculative iteration in flight
+        // while the host reads the flag of the previous one; a queued
+        // iteration after convergence exits at once (device-side guard).
+        if ((rc = iteration(m, dz, true))) return rc;
+        n_enq = 1;
+        if (P->prm.max_iter > 1) {
+          if ((rc = iteration(m, dz, false))) return rc;
+          n_enq = 2;
+        }
+        for (;;) {
+          GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
+          hipEvent_t ev;
+          GMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+          GMM_HIP(hipEventRecord(ev, P->stream));
+          if (n_enq < P->prm.max_iter) {
+            if ((rc = iteration(m, dz, false))) { (void)hipEventDestroy(ev); return rc; }
+            ++n_enq;
+          }
+          GMM_HIP(hipEventSynchronize(ev));
+          GMM_HIP(hipEventDestroy(ev));
+          if (P->h_ctrl->done) break;
+        }
+      }
+      const Ctrl c = *P->h_ctrl;
+      if (c.status == 2) return fail(GMM_ERR_DIVERGED, "non-finite relative change in the MPA iteration");
+      if (c.status == 1) {
+        s.nonconverged_steps++;
+        status = GMM_NOT_CONVERGED;
+      }
+      s.iterations += c.iters;
+      s.evaluations += 1 + (long long)c.iters * m;
+      if (c.iters > s.max_iters_seen) s.max_iters_seen = c.iters;
+      s.last_eps = c.eps;
+      // A~(z0 + m dz) = exp(D m dz) psi_m
+      GMM_HIP(Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0, P->coef, P->nb,
+                               P->nt, nn, m * dz, P->domega, P->stream));
+      s.large_steps++;
+      s.small_steps += m;
+      done += m;
+    }
+    if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_out, &s.photons_out))) return rc;
+    GMM_HIP(Launch<T>::fft_rows(P->logn, -1, (const cplx<T>*)P->psi0, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
+    GMM_HIP(hipStreamSynchronize(P->stream));
+    if (st) *st = s;
+    return status;
+  }
+
+  int nonlinear(const void* At, int count, void* out) {
+    int rc = ensure_workspace(P, count);
+    if (rc) return rc;
+    return eval((const cplx<T>*)At, P->N, count, 0, 0.0, (cplx<T>*)out, nullptr);
+  }
+};
+
+template <typename T>
+int upload_typed(gmm_plan_s* P, const std::vector<double>& ST, const std::vector<std::complex<double>>& tw) {
+  int rc;
+  std::vector<T> st(ST.begin(), ST.end());
+  if ((rc = dev_alloc(&P->const_bytes, (T**)&P->ST, st.size() * sizeof(T)))) return rc;
+  GMM_HIP(hipMemcpy(P->ST, st.data(), st.size() * sizeof(T), hipMemcpyHostToDevice));
+  std::vector<cplx<T>> t(tw.size());
+  for (size_t i = 0; i < tw.size(); ++i) t[i] = cplx<T>{(T)tw[i].real(), (T)tw[i].imag()};
+  if ((rc = dev_alloc(&P->const_bytes, (cplx<T>**)&P->tw, t.size() * sizeof(cplx<T>)))) return rc;
+  GMM_HIP(hipMemcpy(P->tw, t.data(), t.size() * sizeof(cplx<T>), hipMemcpyHostToDevice));
+  return GMM_OK;
+}
+
+template <typename T>
+int build_raman(gmm_plan_s* P, const double* hR) {
+  // weights h_R(k dt) normalised to unit sum; H = FFT_{+}(w); Hs = H / H[0] / Nt
+  const int n = P->nt;
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) sum += hR[k];
+  if (!(std::fabs(sum) > 0.0) || !std::isfinite(sum)) return fail(GMM_ERR_ARG, "h_R samples sum to zero or non-finite");
+  std::vector<std::complex<double>> a(n);
+  for (int k = 0; k < n; ++k) a[k] = hR[k] / sum;
+  host_fft_plus(a);
+  int rc;
+  cplx<double>* dH = nullptr;
+  if ((rc = dev_alloc(&P->const_bytes, &dH, n * sizeof(cplx<double>)))) return rc;
+  std::vector<cplx<double>> h(n);
+  for (int k = 0; k < n; ++k) h[k] = cplx<double>{a[k].real(), a[k].imag()};
+  GMM_HIP(hipMemcpy(dH, h.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
+  if ((rc = dev_alloc(&P->const_bytes, (cplx<T>**)&P->Hs, n * sizeof(cplx<T>)))) return rc;
+  GMM_HIP(Launch<T>::finish_H(dH, (cplx<T>*)P->Hs, n, P->stream));
+  GMM_HIP(hipStreamSynchronize(P->stream));
+  (void)hipFree(dH);
+  P->const_bytes -= (long long)(n * sizeof(cplx<double>));
+  return GMM_OK;
+}
+
+void destroy(gmm_plan_s* P) {
+  if (!P) return;
+  free_workspace(P);
+  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, (void*)P->pidx, (void*)P->pairs, (void*)P->ctrl})
+    if (p) (void)hipFree(p);
+  if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
+  if (P->h_partials) (void)hipHostFree(P->h_partials);
+  delete P;
+}
+
+int create(gmm_plan* out, const gmm_params* p, const double* betas, const double* SK, const double* SR,
+           const double* hR, void* stream) {
+  if (!out || !p || !betas || !SK) return fail(GMM_ERR_ARG, "null argument");
+  *out = nullptr;
+  const int N = p->n_modes, nt = p->nt;
+  if (N < 1) return fail(GMM_ERR_ARG, "n_modes must be >= 1");
+  if (nt < 256 || (nt & (nt - 1))) return fail(GMM_ERR_ARG, "nt must be a power of two >= 256");
+  int logn = 0;
+  while ((1 << logn) < nt) ++logn;
+  if (p->precision != GMM_FP64 && p->precision != GMM_FP32) return fail(GMM_ERR_ARG, "unknown precision");
+  const bool fp64 = p->precision == GMM_FP64;
+  if (fp64 ? !Launch<double>::supports_logn(logn) : !Launch<float>::supports_logn(logn))
+    return fail(GMM_ERR_UNSUPPORTED, "nt outside 2^8..2^15 (2^14 for FP64)");
+  if (p->n_beta < 1) return fail(GMM_ERR_ARG, "n_beta must be >= 1");
+  if (!(p->dt > 0) || !(p->omega0 > 0) || !(p->n2 >= 0) || !(p->fR >= 0 && p->fR <= 1))
+    return fail(GMM_ERR_ARG, "dt, omega0 must be > 0; n2 >= 0; 0 <= fR <= 1");
+  if (p->max_iter < 1 || p->fixed_iters < 0 || !(p->tol >= 0)) return fail(GMM_ERR_ARG, "bad iteration control");
+  const double domega = 2.0 * kPi / (nt * p->dt);
+  if (p->self_steepening && !(p->omega0 - domega * (nt / 2) > 0))
+    return fail(GMM_ERR_ARG, "1 + omega/omega0 <= 0 on the grid: window too fine for the shock term");
+  const bool raman = p->fR > 0;
+  if (raman && !hR) return fail(GMM_ERR_ARG, "hR required when fR > 0");
+  const int Np = N * (N + 1) / 2;
+  const int rpad = ((Np + 63) / 64) * 64;
+  if (rpad > gmm::contract_max_rows())
+    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: packed contraction exceeds 256 rows in this build");
+  // tensor checks: real, S_plmn = S_plnm = S_lpmn
+  const size_t n4 = (size_t)N * N * N * N;
+  double smax = 0;
+  for (size_t i = 0; i < n4; ++i) {
+    if (!std::isfinite(SK[i])) return fail(GMM_ERR_ARG, "non-finite S^K");
+    smax = std::max(smax, std::fabs(SK[i]));
+  }
+  auto S4 = [&](int a, int b, int c, int d) { return SK[(((size_t)a * N + b) * N + c) * N + d]; };
+  const double stol = 1e-12 * smax;
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b)
+      for (int c = 0; c < N; ++c)
+        for (int d = 0; d < N; ++d) {
+          const double v = S4(a, b, c, d);
+          if (std::fabs(v - S4(a, b, d, c)) > stol || std::fabs(v - S4(b, a, c, d)) > stol)
+            return fail(GMM_ERR_TENSOR, "S^K must satisfy S_plmn = S_plnm = S_lpmn for the packed contraction");
+        }
+  if (SR) {
+    for (size_t i = 0; i < n4; ++i)
+      if (std::fabs(SR[i] - SK[i]) > stol)
+        return fail(GMM_ERR_UNSUPPORTED, "S^R different from S^K is not implemented in this build");
+  }
+
+  gmm_plan_s* P = new gmm_plan_s();
+  P->prm = *p;
+  P->N = N;
+  P->nt = nt;
+  P->logn = logn;
+  P->nb = p->n_beta;
+  P->Np = Np;
+  P->rpad = rpad;
+  P->rt = rpad / 64;
+  P->stream = (hipStream_t)stream;
+  P->domega = domega;
+  P->gamma_hat = p->n2 * p->omega0 / kC;
+  P->fp64 = fp64;
+  P->raman = raman;
+  P->esz = fp64 ? 8 : 4;
+
+  int rc = GMM_OK;
+  auto bail = [&](int code) {
+    destroy(P);
+    return code;
+  };
+  // dispersion coefficients beta_n / n!
+  std::vector<double> coef((size_t)N * P->nb);
+  for (int q = 0; q < N; ++q) {
+    double fact = 1.0;
+    for (int n = 0; n < P->nb; ++n) {
+      if (n > 0) fact *= n;
+      const double b = betas[(size_t)q * P->nb + n];
+      if (!std::isfinite(b)) return bail(fail(GMM_ERR_ARG, "non-finite beta"));
+      coef[(size_t)q * P->nb + n] = b / fact;
+    }
+  }
+  if ((rc = dev_alloc(&P->const_bytes, &P->coef, coef.size() * sizeof(double)))) return bail(rc);
+  if (hipMemcpy(P->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "copy of dispersion coefficients failed"));
+  // mode pairs (m <= n, lexicographic) and pair index table
+  std::vector<int2> pairs;
+  std::vector<int> pidx((size_t)N * N);
+  for (int m = 0; m < N; ++m)
+    for (int n = m; n < N; ++n) {
+      pidx[(size_t)m * N + n] = pidx[(size_t)n * N + m] = (int)pairs.size();
+      pairs.push_back(make_int2(m, n));
+    }
+  // packed coupling matrix  S^_{(p,l),(m,n)} = w_mn S_plmn, w = 1 (m = n) or 2; stored transposed
+  std::vector<double> ST((size_t)rpad * rpad, 0.0);
+  for (int r = 0; r < Np; ++r)
+    for (int q = 0; q < Np; ++q) {
+      const int2 pl = pairs[r], mn = pairs[q];
+      const double w = mn.x == mn.y ? 1.0 : 2.0;
+      ST[(size_t)q * rpad + r] = w * S4(pl.x, pl.y, mn.x, mn.y);
+    }
+  // twiddles exp(-2 pi i m / nt)
+  std::vector<std::complex<double>> tw(nt);
+  for (int m = 0; m < nt; ++m) tw[m] = std::polar(1.0, -2.0 * kPi * (double)m / nt);
+  if ((rc = dev_alloc(&P->const_bytes, &P->pidx, pidx.size() * sizeof(int)))) return bail(rc);
+  if ((rc = dev_alloc(&P->const_bytes, &P->pairs, pairs.size() * sizeof(int2)))) return bail(rc);
+  if (hipMemcpy(P->pidx, pidx.data(), pidx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "copy of pair tables failed"));
+  rc = fp64 ? upload_typed<double>(P, ST, tw) : upload_typed<float>(P, ST, tw);
+  if (rc) return bail(rc);
+  if (raman) {
+    rc = fp64 ? build_raman<double>(P, hR) : build_raman<float>(P, hR);
+    if (rc) return bail(rc);
+  }
+  if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
+  if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&P->h_partials, 2 * sizeof(double) * gmm::trapz_blocks((long)N * nt),
+                    hipHostMallocDefault) != hipSuccess)
+    return bail(fail(GMM_ERR_NOMEM, "pinned host allocation failed"));
+  *out = P;
+  g_last_error.clear();
+  return GMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmm_plan_create(gmm_plan* out, const gmm_params* p, const double* betas, const double* SK, const double* SR,
+                    const double* hR, void* stream) {
+  try {
+    return create(out, p, betas, SK, SR, hR, stream);
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_propagate(gmm_plan plan, const void* A0, double L, double dz, int M, void* Aout, gmm_stats* st) {
+  if (!plan || !A0 || !Aout) return fail(GMM_ERR_ARG, "null argument");
+  if (!(L > 0) || !(dz > 0) || !std::isfinite(L) || !std::isfinite(dz)) return fail(GMM_ERR_ARG, "L and dz must be > 0");
+  if (M < 1) return fail(GMM_ERR_ARG, "M must be >= 1");
+  if (L / dz > 1e12) return fail(GMM_ERR_ARG, "too many small steps");
+  try {
+    int rc = plan->fp64 ? Runner<double>{plan}.propagate(A0, L, dz, M, Aout, st)
+                        : Runner<float>{plan}.propagate(A0, L, dz, M, Aout, st);
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out) {
+  if (!plan || !At || !out) return fail(GMM_ERR_ARG, "null argument");
+  if (count < 1) return fail(GMM_ERR_ARG, "count must be >= 1");
+  if (At == out) return fail(GMM_ERR_ARG, "out must not alias At");
+  return plan->fp64 ? Runner<double>{plan}.nonlinear(At, count, out) : Runner<float>{plan}.nonlinear(At, count, out);
+}
+
+int gmm_plan_destroy(gmm_plan plan) {
+  destroy(plan);
+  return GMM_OK;
+}
+
+const char* gmm_last_error(void) { return g_last_error.c_str(); }
+
+long long gmm_plan_device_bytes(gmm_plan plan) { return plan ? plan->const_bytes + plan->ws_bytes : 0; }
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libgmmpa.so (C ABI declared in include/gmmpa.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+kernels of the library.  PyTorch provides device memory and the HIP stream.
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmmpa.so")
+
+GMM_OK = 0
+GMM_NOT_CONVERGED = 1
+GMM_ERR_ARG = -1
+GMM_ERR_NOMEM = -2
+GMM_ERR_TENSOR = -3
+GMM_ERR_HIP = -4
+GMM_ERR_UNSUPPORTED = -5
+GMM_ERR_DIVERGED = -6
+GMM_FP64 = 0
+GMM_FP32 = 1
+
+EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_nonlinear", "gmm_plan_destroy", "gmm_last_error",
+           "gmm_plan_device_bytes")
+
+
+class gmm_params(ctypes.Structure):
+    _fields_ = [("n_modes", ctypes.c_int), ("nt", ctypes.c_int), ("n_beta", ctypes.c_int),
+                ("dt", ctypes.c_double), ("omega0", ctypes.c_double), ("n2", ctypes.c_double),
+                ("fR", ctypes.c_double), ("self_steepening", ctypes.c_int), ("precision", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+
+
+class gmm_stats(ctypes.Structure):
+    _fields_ = [("large_steps", ctypes.c_int), ("small_steps", ctypes.c_int),
+                ("iterations", ctypes.c_longlong), ("evaluations", ctypes.c_longlong),
+                ("max_iters_seen", ctypes.c_int), ("nonconverged_steps", ctypes.c_int),
+                ("last_eps", ctypes.c_double), ("dz_used", ctypes.c_double),
+                ("energy_in", ctypes.c_double), ("energy_out", ctypes.c_double),
+                ("photons_in", ctypes.c_double), ("photons_out", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgmmpa.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1708_05324_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dbl, ci = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    lib.gmm_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(gmm_params), vp, vp, vp, vp, vp]
+    lib.gmm_plan_create.restype = ci
+    lib.gmm_propagate.argtypes = [vp, vp, dbl, dbl, ci, vp, ctypes.POINTER(gmm_stats)]
+    lib.gmm_propagate.restype = ci
+    lib.gmm_nonlinear.argtypes = [vp, vp, ci, vp]
+    lib.gmm_nonlinear.restype = ci
+    lib.gmm_plan_destroy.argtypes = [vp]
+    lib.gmm_plan_destroy.restype = ci
+    lib.gmm_last_error.argtypes = []
+    lib.gmm_last_error.restype = ctypes.c_char_p
+    lib.gmm_plan_device_bytes.argtypes = [vp]
+    lib.gmm_plan_device_bytes.restype = ctypes.c_longlong
+    _lib = lib
+    return lib
+
+
+class GmmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gmmpa error {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int, allow=(GMM_OK,)) -> int:
+    if code not in allow:
+        raise GmmError(code, load_library().gmm_last_error().decode())
+    return code
+
+
+def _host_ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class Result:
+    field: object          # torch tensor [N][Nt] on the device
+    status: int
+    stats: dict
+
+
+class Plan:
+    """A propagation plan: the inputs of Eq. (1) bound to one GPU stream.
+
+    precision: "fp64" (complex128 fields) or "fp32" (complex64 fields).
+    """
+
+    def __init__(self, betas, SK, hR=None, *, nt: int, dt: float, omega0: float, n2: float, fR: float,
+                 self_steepening: int = 1, precision: str = "fp64", tol: float = 1e-12, max_iter: int = 20,
+                 fixed_iters: int = 0, SR=None, stream=None):
+        import torch
+        self.lib = load_library()
+        betas = np.ascontiguousarray(np.atleast_2d(np.asarray(betas, dtype=np.float64)))
+        SK = np.ascontiguousarray(np.asarray(SK, dtype=np.float64))
+        self.n_modes = betas.shape[0]
+        if SK.size != self.n_modes ** 4:
+            raise ValueError("SK must hold N^4 values")
+        SR = None if SR is None else np.ascontiguousarray(np.asarray(SR, dtype=np.float64))
+        hR = None if hR is None else np.ascontiguousarray(np.asarray(hR, dtype=np.float64))
+        if hR is not None and hR.size != nt:
+            raise ValueError("hR must hold nt samples")
+        self.precision = precision
+        self.nt = nt
+        self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        prec = {"fp64": GMM_FP64, "fp32": GMM_FP32}[precision]
+        self.params = gmm_params(self.n_modes, nt, betas.shape[1], dt, omega0, n2, fR, int(self_steepening),
+                                 prec, tol, max_iter, fixed_iters)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        self._keep = (betas, SK, SR, hR)
+        _check(self.lib.gmm_plan_create(ctypes.byref(handle), ctypes.byref(self.params), _host_ptr(betas),
+                                        _host_ptr(SK), _host_ptr(SR), _host_ptr(hR),
+                                        ctypes.c_void_p(stream.cuda_stream)))
+        self.handle = handle
+
+    def _check_field(self, A):
+        import torch
+        if not isinstance(A, torch.Tensor) or not A.is_cuda:
+            raise TypeError("fields must be torch tensors on the GPU")
+        if A.dtype != self.dtype or not A.is_contiguous():
+            raise TypeError(f"fields must be contiguous {self.dtype}")
+
+    def propagate(self, A0, L: float, dz: float, M: int, out=None) -> Result:
+        import torch
+        self._check_field(A0)
+        if tuple(A0.shape) != (self.n_modes, self.nt):
+            raise ValueError("A0 must be [N][Nt]")
+        if out is None:
+            out = torch.empty_like(A0)
+        st = gmm_stats()
+        rc = self.lib.gmm_propagate(self.handle, ctypes.c_void_p(A0.data_ptr()), float(L), float(dz), int(M),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+        _check(rc, allow=(GMM_OK, GMM_NOT_CONVERGED))
+        return Result(out, rc, st.as_dict())
+
+    def nonlinear(self, At, out=None):
+        """Integrand factor of Eq. (MPA_eq) for spectra At [count][N][Nt]."""
+        import torch
+        self._check_field(At)
+        if At.dim() == 2:
+            At = At.unsqueeze(0)
+        if tuple(At.shape[1:]) != (self.n_modes, self.nt):
+            raise ValueError("At must be [count][N][Nt]")
+        if out is None:
+            out = torch.empty_like(At)
+        _check(self.lib.gmm_nonlinear(self.handle, ctypes.c_void_p(At.data_ptr()), int(At.shape[0]),
+                                      ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def device_bytes(self) -> int:
+        return int(self.lib.gmm_plan_device_bytes(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.gmm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_from_workload(w, precision: str = "fp64", **kw) -> Plan:
+    """Plan for a synthetic workload object (see paper_1708_05324_amd.synth)."""
+    return Plan(w.betas, w.S, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,
+                self_steepening=w.self_steepening, precision=precision, **kw)

@@ -1,0 +1,196 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Error measure: max |A - A_ref| / max |A_ref| over all modes and samples (the
+field error normalised by the global peak).  Tolerances: FP64 paths 1e-11
+(operator) / 1e-10 (propagation); FP32 paths 2e-5 / 1e-5.  The FP32 bound is
+the spec field tolerance; the operator bound allows the sum over up to
+Np^2 terms in FP32 (about Np * 2^-24 * max term).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gmmnlse as O
+from paper_1708_05324_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = {"fp64": 1e-11, "fp32": 2e-5}
+TOL_PROP = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_05324_amd import gmmpa
+    gmmpa.load_library()
+    return torch
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def to_dev(torch, x, prec):
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt)
+
+
+def small_workload(N_groups=2, nt=256, fR=0.18, s=1, P=2e5, dt=80e-15, cfg=7):
+    return synth.grin_workload(cfg, N_groups, nt, dt, "sech", 200e-15, peak_power=P, fR=fR,
+                               self_steepening=s, M=5, L=0.02)
+
+
+def make_plan(w, prec, **kw):
+    from paper_1708_05324_amd import gmmpa
+    return gmmpa.plan_from_workload(w, precision=prec, **kw)
+
+
+CASES = [  # (groups, nt, fR, shock, dt)
+    (1, 256, 0.0, 0, 80e-15),        # one mode: transforms + pair product only
+    (2, 256, 0.0, 0, 80e-15),        # 3 modes, Kerr only
+    (2, 512, 0.18, 1, 40e-15),       # 3 modes, Raman + shock
+    (3, 1024, 0.18, 1, 20e-15),      # 6 modes
+    (5, 2048, 0.18, 1, 10e-15),      # 15 modes: 120 packed rows (two row tiles per wave)
+    (6, 256, 0.18, 1, 80e-15),       # 21 modes: 231 rows (four row tiles per wave)
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_s{c[3]}")
+def test_nonlinear_operator_matches_oracle(torch_gpu, prec, case):
+    torch = torch_gpu
+    g, nt, fR, s, dt = case
+    w = small_workload(N_groups=g, nt=nt, fR=fR, s=s, dt=dt)
+    m = O.model_from_workload(w)
+    ops = O._Ops(m, nt)
+    count = 3
+    spectra = []
+    for c in range(count):                       # three different fields: pulse, chirped, random
+        A = w.A0 * np.exp(1j * 0.3 * c * np.arange(nt) / nt) + 0.2 * c * synth.random_fields(c, w.n_modes, nt,
+                                                                                              scale=100.0)
+        spectra.append(O.to_spectrum(A))
+    At = np.stack(spectra)
+    ref = np.stack([ops.N(a) for a in spectra])
+    plan = make_plan(w, prec)
+    got = plan.nonlinear(to_dev(torch, At, prec)).cpu().numpy()
+    err = relmax(got, ref)
+    print(f"[{prec} N={w.n_modes} nt={nt}] operator error {err:.3e}", flush=True)
+    assert err < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_linear_propagation_is_exact(torch_gpu, prec):
+    """gamma = 0: the output is exp(D_w L) A~(0) (Eq. (cov) with psi constant)."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.0, s=0, dt=20e-15)
+    w.betas[:, 1] *= 1e3          # visible walk-off
+    w.n2 = 0.0
+    m = O.model_from_workload(w)
+    L = 0.0123
+    om = O.omega_grid(w.nt, w.dt)
+    exact = O.to_time(np.exp(O.dispersion_operator(w.betas, om) * L) * O.to_spectrum(w.A0))
+    plan = make_plan(w, prec, tol=1e-12)
+    res = plan.propagate(to_dev(torch, w.A0, prec), L, L / 20, 5)
+    err = relmax(res.field.cpu().numpy(), exact)
+    print(f"[{prec}] linear error {err:.3e} stats {res.stats}", flush=True)
+    assert err < (1e-12 if prec == "fp64" else 2e-6)
+    assert res.stats["small_steps"] == 20 and res.stats["large_steps"] == 4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,nsteps", [(5, 15), (4, 10)])   # 10 = 2 x 4 + a last large step of 2
+def test_propagation_fixed_iterations_matches_oracle(torch_gpu, prec, M, nsteps):
+    torch = torch_gpu
+    w = small_workload(N_groups=2, nt=256, fR=0.18, s=1)
+    m = O.model_from_workload(w)
+    L = nsteps * w.dz
+    ref = O.mpa_propagate(w.A0, m, L, w.dz, M, fixed_iters=3)
+    plan = make_plan(w, prec, fixed_iters=3)
+    res = plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, M)
+    err = relmax(res.field.cpu().numpy(), ref)
+    print(f"[{prec} M={M}] propagation error {err:.3e}", flush=True)
+    assert err < TOL_PROP[prec]
+    assert res.stats["iterations"] == 3 * math.ceil(nsteps / M)
+
+
+def test_propagation_tolerance_mode_matches_oracle(torch_gpu):
+    """Same threshold, same iteration counts and result as the oracle (FP64)."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    m = O.model_from_workload(w)
+    L = 20 * w.dz
+    ref, st = O.mpa_propagate(w.A0, m, L, w.dz, 10, tol=1e-9, return_stats=True)
+    plan = make_plan(w, "fp64", tol=1e-9)
+    res = plan.propagate(to_dev(torch, w.A0, "fp64"), L, w.dz, 10)
+    assert relmax(res.field.cpu().numpy(), ref) < 1e-10
+    assert res.stats["iterations"] == sum(st.iterations)
+    assert res.stats["max_iters_seen"] == max(st.iterations)
+    E = O.energy(w.A0, w.dt)
+    assert res.stats["energy_in"] == pytest.approx(E, rel=1e-12)
+    Pn = O.photon_number(ref, w.dt, w.omega0)
+    assert res.stats["photons_out"] == pytest.approx(Pn, rel=1e-10)
+
+
+def test_nonconvergence_is_reported(torch_gpu):
+    from paper_1708_05324_amd import gmmpa
+    torch = torch_gpu
+    w = small_workload(N_groups=2, nt=256, fR=0.18, s=1, P=2e8)
+    plan = make_plan(w, "fp64", tol=1e-14, max_iter=3)
+    res = plan.propagate(to_dev(torch, w.A0, "fp64"), 40 * w.dz, w.dz, 40)
+    assert res.status == gmmpa.GMM_NOT_CONVERGED
+    assert res.stats["nonconverged_steps"] >= 1 and res.stats["max_iters_seen"] == 3
+
+
+def test_repeated_runs_are_bitwise_identical(torch_gpu):
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    plan = make_plan(w, "fp32", tol=1e-6)
+    A0 = to_dev(torch, w.A0, "fp32")
+    a = plan.propagate(A0, 20 * w.dz, w.dz, 10).field.cpu().numpy()
+    b = plan.propagate(A0, 20 * w.dz, w.dz, 10).field.cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ workload shapes
+@pytest.fixture(scope="module")
+def metric_reference():
+    """Oracle result for one large step (M = 10, two iterations) of the 15-mode,
+    2^14-sample Kerr + Raman + shock workload."""
+    w = synth.config3()
+    m = O.model_from_workload(w)
+    ref = O.mpa_propagate(w.A0, m, 10 * w.dz, w.dz, 10, fixed_iters=2)
+    return w, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_metric_workload_one_large_step(torch_gpu, metric_reference, prec):
+    torch = torch_gpu
+    w, ref = metric_reference
+    plan = make_plan(w, prec, fixed_iters=2)
+    res = plan.propagate(to_dev(torch, w.A0, prec), 10 * w.dz, w.dz, 10)
+    err = relmax(res.field.cpu().numpy(), ref)
+    print(f"[{prec} N=15 nt=16384 M=10] error {err:.3e}", flush=True)
+    assert err < TOL_PROP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_small_workloads_several_large_steps(torch_gpu, prec, cfg):
+    """3 modes / 2^10 (Kerr only, the stated 1 mm step) and 6 modes / 2^13
+    (Raman + shock, step from the z_NL/z_IM rule), three large steps each."""
+    torch = torch_gpu
+    w = synth.config1() if cfg == 1 else synth.config2()
+    m = O.model_from_workload(w)
+    L = 3 * w.M * w.dz
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    ref, st = O.mpa_propagate(w.A0, m, L, w.dz, w.M, tol=tol, max_iter=40, return_stats=True)
+    plan = make_plan(w, prec, tol=tol, max_iter=40)
+    res = plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, w.M)
+    err = relmax(res.field.cpu().numpy(), ref)
+    print(f"[{prec} cfg{cfg}] error {err:.3e} iters gpu {res.stats['iterations']} oracle {sum(st.iterations)}",
+          flush=True)
+    assert err < (1e-8 if prec == "fp64" else 2e-5)
