@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the massively parallel GMMNLSE propagation step on one MI355X.
+
+Workload: parabolic GRIN fibre, 15 modes (Hermite-Gauss groups 0-4), Nt = 2^14
+samples over 40 ps, Kerr + Raman (fR = 0.18) + self-steepening, 200 fs
+Gaussian of 100 nJ spread evenly over the modes with seeded phases, M = 10
+small steps per large step, dz = min(z_NL/200, z_IM/5) = 9.13 um.
+
+One benchmark step is one MPA large step (M small steps dz, iterated to the
+tolerance).  The metric is converged small steps dz per second.  Prints one
+JSON line.  Use --gpus 1 only: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "mfma_fp32_TFLOPs": 157.3,
+    "mfma_fp64_TFLOPs": 78.6,
+    # vector ALU with packed FP32 disabled: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
+    "alu_fp32_TFLOPs": 78.6,
+    "alu_fp64_TFLOPs": 78.6,
+}
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+def work_per_eval(kind: str, N: int, Nt: int, prec: str) -> dict:
+    """Algorithmic work of one kernel kind for one sub-step integrand."""
+    Np = N * (N + 1) // 2
+    rs = 8 if prec == "fp64" else 4
+    cs = 2 * rs
+    fft = 5.0 * Nt * math.log2(Nt)
+    if kind == "contract":
+        return {"bound": "mfma", "flops": 2.0 * Np * Np * Nt, "bytes": Np * Nt * rs + 2 * N * Nt * cs}
+    if kind == "pairs_raman":
+        return {"bound": "alu", "flops": math.ceil(Np / 2) * 2 * fft, "bytes": N * Nt * cs + Np * Nt * rs}
+    if kind in ("phase_to_time", "spectral_out"):
+        return {"bound": "hbm", "flops": N * fft, "bytes": 2 * N * Nt * cs}
+    if kind == "trapz":
+        return {"bound": "hbm", "flops": 0.0, "bytes": 3 * N * Nt * cs}
+    return {"bound": "hbm", "flops": 0.0, "bytes": 0.0}
+
+
+def read_traffic(kind: str, workload: str, prec: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1708_05324_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(src, "*"))):
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", f"counters_{kind}_{workload}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel_sources_sha:\s*([0-9a-f]+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_b) or m_sha.group(1) != sha:
+        return None
+    return float(m_b.group(1))
+
+
+def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool):
+    import torch
+    from paper_1708_05324_amd import gmmpa
+    plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30)
+    dtype = torch.complex128 if prec == "fp64" else torch.complex64
+    A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
+    Ls = w.M * w.dz
+    if warmup > 0:
+        A = plan.propagate(A, warmup * Ls, w.dz, w.M).field
+    if profile:
+        plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.propagate(A, steps * Ls, w.dz, w.M)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read() if profile else None
+    plan.profile(False)
+    lat = []
+    solve_L = 11 * Ls                      # one "solve": 110 small steps (about 1 mm)
+    B = res.field
+    for _ in range(latency_solves):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        B = plan.propagate(B, solve_L, w.dz, w.M).field
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    st = res.stats
+    out = {
+        "seconds": t1 - t0,
+        "small_steps_per_s": st["small_steps"] / (t1 - t0),
+        "ms_per_large_step": (t1 - t0) / st["large_steps"] * 1e3,
+        "iterations_per_large_step": st["iterations"] / st["large_steps"],
+        "evaluations_per_s": st["evaluations"] / (t1 - t0),
+        "nonconverged_steps": st["nonconverged_steps"],
+        "stats": st,
+        "prof": prof,
+    }
+    if lat:
+        lat.sort()
+        out["latency_ms_p50"] = lat[len(lat) // 2]
+        out["latency_ms_p99"] = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+        out["latency_small_steps"] = int(round(solve_L / w.dz))
+    plan.close()
+    return out
+
+
+def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str):
+    """Roofline entry of the kernel kind with the largest total time."""
+    kind = max(prof, key=lambda k: prof[k][0])
+    total_ms, launches = prof[kind]
+    evals = stats["evaluations"]          # sub-step integrands = units processed by all counted launches
+    wk = work_per_eval(kind, N, Nt, prec)
+    sec = total_ms * 1e-3
+    if wk["bound"] == "mfma":
+        achieved = wk["flops"] * evals / sec / 1e12
+        peak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else "mfma_fp32_TFLOPs"]
+        unit = "TFLOP/s"
+    elif wk["bound"] == "alu":
+        achieved = wk["flops"] * evals / sec / 1e12
+        peak = PEAKS["alu_fp64_TFLOPs" if prec == "fp64" else "alu_fp32_TFLOPs"]
+        unit = "TFLOP/s"
+    else:
+        achieved = wk["bytes"] * evals / sec / 1e9
+        peak = PEAKS["hbm_GBps"]
+        unit = "GB/s"
+    return {
+        "kernel": kind,
+        "bound": wk["bound"],
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": unit,
+        "frac": round(achieved / peak, 4),
+        "traffic": read_traffic(kind, workload, prec),
+        "avg_launch_us": round(total_ms / launches * 1e3, 2) if launches else None,
+        "launches": launches,
+        "units_per_launch": round(evals / launches, 3) if launches else None,
+    }
+
+
+def cpu_baseline(w, max_seconds: float = 30.0):
+    """The FP64 oracle on the host: one large step (M small steps) of the workload."""
+    from oracle import gmmnlse as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    m = O.model_from_workload(w)
+    t0 = time.perf_counter()
+    _, st = O.mpa_propagate(w.A0, m, w.M * w.dz, w.dz, w.M, tol=TOL["fp64"], max_iter=30, return_stats=True)
+    sec = time.perf_counter() - t0
+    return {"value": round(w.M / sec, 4), "unit": "small steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one large step ({w.M} small steps of {w.dz * 1e6:.2f} um) of the same workload, FP64, "
+                      f"tol 1e-12 ({st.iterations[0]} iterations, {st.evaluations} evaluations) in {sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40, help="timed large steps")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed large steps")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-solves", type=int, default=20)
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1708_05324_amd import gmmpa, synth
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    gmmpa.load_library()
+    w = synth.config3()
+    N, Nt = w.n_modes, w.nt
+    workload = "grin15_raman_nt16384"
+
+    main_run = run_gpu(args.precision, w, args.steps, args.warmup, args.latency_solves, not args.no_profile)
+    extra = {}
+    if not args.no_compare:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        o = run_gpu(other, w, max(4, args.steps // 4), 1, 0, False)
+        extra[other] = {"small_steps_per_s": round(o["small_steps_per_s"], 2),
+                        "evaluations_per_s": round(o["evaluations_per_s"], 2),
+                        "iterations_per_large_step": round(o["iterations_per_large_step"], 3),
+                        "ms_per_large_step": round(o["ms_per_large_step"], 4)}
+    line = {
+        "metric": "MPA steps/s at N=15 modes, Nt=2^14 (BF16/FP32 vs FP64); p50/p99 solve latency",
+        "value": round(main_run["small_steps_per_s"], 2),
+        "unit": "small steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_large_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n_modes": N, "nt": Nt, "window_ps": round(Nt * w.dt * 1e12, 3),
+                   "M": w.M, "dz_um": round(w.dz * 1e6, 4), "tol": TOL[args.precision], "fR": w.fR,
+                   "self_steepening": w.self_steepening, "step": "one MPA large step (M small steps)",
+                   "parallelism": "single GPU"},
+        "iterations_per_large_step": round(main_run["iterations_per_large_step"], 3),
+        "evaluations_per_s": round(main_run["evaluations_per_s"], 2),
+        "latency_ms_p50": round(main_run.get("latency_ms_p50", float("nan")), 3),
+        "latency_ms_p99": round(main_run.get("latency_ms_p99", float("nan")), 3),
+        "latency_solve": f"{main_run.get('latency_small_steps')} small steps per solve",
+        "compare": extra,
+    }
+    if main_run["prof"]:
+        line["roofline"] = roofline(main_run["prof"], main_run["stats"], N, Nt, args.precision, workload)
+        line["kernel_ms_per_large_step"] = {k: round(v[0] / main_run["stats"]["large_steps"], 4)
+                                            for k, v in main_run["prof"].items()}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

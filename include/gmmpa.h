@@ -137,6 +137,25 @@ const char* gmm_last_error(void);
 /* Device bytes currently held by the plan (constants + workspace). */
 long long gmm_plan_device_bytes(gmm_plan plan);
 
+/*
+ * Per-kernel timing with HIP events on the plan's stream (for benchmarks).
+ * gmm_profile_enable(plan, 1) clears the totals and brackets every later
+ * kernel launch with two events; launches of queued iterations that exit at
+ * once (the large step had already converged) are not counted.
+ * gmm_profile_read copies, for the first n_kinds kernel kinds below, the
+ * summed duration in ms and the number of counted launches.
+ */
+#define GMM_PROF_PHASE 0    /* phase factors + inverse transform (sub-step fields) */
+#define GMM_PROF_PAIRS 1    /* pair products + Raman convolution */
+#define GMM_PROF_CONTRACT 2 /* coupling contraction (MFMA) + mode projection */
+#define GMM_PROF_SPECTRAL 3 /* forward transform + shock + back-phase */
+#define GMM_PROF_TRAPZ 4    /* cumulative trapezoid + FP64 partial norms */
+#define GMM_PROF_NORM 5     /* norm reduction + stop decision */
+#define GMM_PROF_CLOSE 6    /* large-step close */
+#define GMM_PROF_KINDS 7
+int gmm_profile_enable(gmm_plan plan, int on);
+int gmm_profile_read(gmm_plan plan, double* total_ms, long long* launches, int n_kinds);
+
 #ifdef __cplusplus
 }
 #endif

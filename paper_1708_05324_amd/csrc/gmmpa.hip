@@ -34,6 +34,23 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(GMM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Queue a kernel launch; with profiling on, bracket it with two events.
+#define GMM_LAUNCH(P, KIND, call)                                                  \
+  do {                                                                             \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                                         \
+    if ((P)->prof.on) {                                                            \
+      a_ = (P)->prof.get();                                                        \
+      b_ = (P)->prof.get();                                                        \
+      if (!a_ || !b_) return fail(GMM_ERR_HIP, "hipEventCreate failed");           \
+      GMM_HIP(hipEventRecord(a_, (P)->stream));                                    \
+    }                                                                              \
+    GMM_HIP(call);                                                                 \
+    if ((P)->prof.on) {                                                            \
+      GMM_HIP(hipEventRecord(b_, (P)->stream));                                    \
+      (P)->prof.recs.push_back({a_, b_, (KIND), (P)->prof.cur_step, (P)->prof.cur_iter}); \
+    }                                                                              \
+  } while (0)
+
 constexpr double kC = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -61,6 +78,57 @@ void host_fft_plus(std::vector<std::complex<double>>& a) {
 
 }  // namespace
 
+// Per-kernel HIP-event timing, off by default.  Every launch is bracketed by
+// two events on the plan's stream; launches of speculatively queued
+// iterations that exit at once (the step had already converged) are dropped
+// when the records are read, so averages cover launches that did work.
+struct GmmProfiler {
+  struct Rec {
+    hipEvent_t a, b;
+    int kind, step, iter;
+  };
+  bool on = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> step_iters;  // iterations that ran, per large step of the current propagate
+  int cur_step = 0, cur_iter = 0;
+  double ms[GMM_PROF_KINDS] = {};
+  long long n[GMM_PROF_KINDS] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void collect() {  // call after the stream is synchronised
+    for (const Rec& r : recs) {
+      const bool valid = r.iter == 0 || (r.step < (int)step_iters.size() && r.iter <= step_iters[r.step]);
+      float t = 0.f;
+      if (valid && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.kind] += t;
+        n[r.kind] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+    step_iters.clear();
+    cur_step = cur_iter = 0;
+  }
+  void reset() {
+    for (int k = 0; k < GMM_PROF_KINDS; ++k) ms[k] = 0, n[k] = 0;
+  }
+  ~GmmProfiler() {
+    for (auto& r : recs) pool.push_back(r.a), pool.push_back(r.b);
+    for (hipEvent_t e : pool)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 struct gmm_plan_s {
   gmm_params prm{};
   int N = 0, nt = 0, logn = 0, nb = 0, Np = 0, rt = 0, rpad = 0;
@@ -83,6 +151,7 @@ struct gmm_plan_s {
   Ctrl* h_ctrl = nullptr;         // pinned
   double* h_partials = nullptr;   // pinned
   long long const_bytes = 0, ws_bytes = 0;
+  GmmProfiler prof;
 };
 
 namespace {
@@ -144,13 +213,13 @@ struct Runner {
     if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
     if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
     cplx<T>* W = (cplx<T>*)P->work;
-    GMM_HIP(Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
+    GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                      tw(), ctrl, P->stream));
-    GMM_HIP(Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
+    GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                              (T)(1.0 - P->prm.fR), (T)P->prm.fR, (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
-    GMM_HIP(Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N, P->Np, P->nt, count, ctrl,
+    GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N, P->Np, P->nt, count, ctrl,
                                 P->stream));
-    GMM_HIP(Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
+    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                     P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), ctrl,
                                     P->stream));
     return GMM_OK;
@@ -161,9 +230,9 @@ struct Runner {
     const cplx<T>* src = first ? (const cplx<T>*)P->psi0 : (const cplx<T>*)P->psi;
     int rc = eval(src, first ? 0 : P->N, m, 1, dz, (cplx<T>*)P->work, P->ctrl);
     if (rc) return rc;
-    GMM_HIP(Launch<T>::trapz((const cplx<T>*)P->psi0, (const cplx<T>*)P->I0, (const cplx<T>*)P->work,
+    GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, (const cplx<T>*)P->I0, (const cplx<T>*)P->work,
                              (cplx<T>*)P->psi, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl, P->stream));
-    GMM_HIP(gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol, P->prm.fixed_iters,
+    GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol, P->prm.fixed_iters,
                                    P->prm.max_iter, P->stream));
     return GMM_OK;
   }
@@ -210,17 +279,21 @@ struct Runner {
       if ((rc = eval((const cplx<T>*)P->psi0, 0, 1, 0, dz, (cplx<T>*)P->I0, nullptr))) return rc;
       int n_enq = 0;
       if (P->prm.fixed_iters > 0) {
-        for (; n_enq < P->prm.fixed_iters; ++n_enq)
+        for (; n_enq < P->prm.fixed_iters; ++n_enq) {
+          P->prof.cur_iter = n_enq + 1;
           if ((rc = iteration(m, dz, n_enq == 0))) return rc;
+        }
         GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
         GMM_HIP(hipStreamSynchronize(P->stream));
       } else {
         // Queue two iterations, then keep one speculative iteration in flight
         // while the host reads the flag of the previous one; a queued
         // iteration after convergence exits at once (device-side guard).
+        P->prof.cur_iter = 1;
         if ((rc = iteration(m, dz, true))) return rc;
         n_enq = 1;
         if (P->prm.max_iter > 1) {
+          P->prof.cur_iter = 2;
           if ((rc = iteration(m, dz, false))) return rc;
           n_enq = 2;
         }
@@ -230,6 +303,7 @@ struct Runner {
           GMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
           GMM_HIP(hipEventRecord(ev, P->stream));
           if (n_enq < P->prm.max_iter) {
+            P->prof.cur_iter = n_enq + 1;
             if ((rc = iteration(m, dz, false))) { (void)hipEventDestroy(ev); return rc; }
             ++n_enq;
           }
@@ -239,6 +313,8 @@ struct Runner {
         }
       }
       const Ctrl c = *P->h_ctrl;
+      P->prof.cur_iter = 0;
+      P->prof.step_iters.push_back(c.iters);
       if (c.status == 2) return fail(GMM_ERR_DIVERGED, "non-finite relative change in the MPA iteration");
       if (c.status == 1) {
         s.nonconverged_steps++;
@@ -249,15 +325,17 @@ struct Runner {
       if (c.iters > s.max_iters_seen) s.max_iters_seen = c.iters;
       s.last_eps = c.eps;
       // A~(z0 + m dz) = exp(D m dz) psi_m
-      GMM_HIP(Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0, P->coef, P->nb,
+      GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0, P->coef, P->nb,
                                P->nt, nn, m * dz, P->domega, P->stream));
       s.large_steps++;
       s.small_steps += m;
       done += m;
+      P->prof.cur_step++;
     }
     if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_out, &s.photons_out))) return rc;
     GMM_HIP(Launch<T>::fft_rows(P->logn, -1, (const cplx<T>*)P->psi0, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
     GMM_HIP(hipStreamSynchronize(P->stream));
+    if (P->prof.on) P->prof.collect();
     if (st) *st = s;
     return status;
   }
@@ -265,7 +343,13 @@ struct Runner {
   int nonlinear(const void* At, int count, void* out) {
     int rc = ensure_workspace(P, count);
     if (rc) return rc;
-    return eval((const cplx<T>*)At, P->N, count, 0, 0.0, (cplx<T>*)out, nullptr);
+    P->prof.cur_iter = 0;
+    rc = eval((const cplx<T>*)At, P->N, count, 0, 0.0, (cplx<T>*)out, nullptr);
+    if (rc == GMM_OK && P->prof.on) {
+      GMM_HIP(hipStreamSynchronize(P->stream));
+      P->prof.collect();
+    }
+    return rc;
   }
 };
 
@@ -483,5 +567,21 @@ int gmm_plan_destroy(gmm_plan plan) {
 const char* gmm_last_error(void) { return g_last_error.c_str(); }
 
 long long gmm_plan_device_bytes(gmm_plan plan) { return plan ? plan->const_bytes + plan->ws_bytes : 0; }
+
+int gmm_profile_enable(gmm_plan plan, int on) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  plan->prof.on = on != 0;
+  plan->prof.reset();
+  return GMM_OK;
+}
+
+int gmm_profile_read(gmm_plan plan, double* total_ms, long long* launches, int n_kinds) {
+  if (!plan || !total_ms || !launches || n_kinds < 1) return fail(GMM_ERR_ARG, "bad profile_read arguments");
+  for (int k = 0; k < n_kinds; ++k) {
+    total_ms[k] = k < GMM_PROF_KINDS ? plan->prof.ms[k] : 0.0;
+    launches[k] = k < GMM_PROF_KINDS ? plan->prof.n[k] : 0;
+  }
+  return GMM_OK;
+}
 
 }  // extern "C"

@@ -28,7 +28,8 @@ GMM_FP64 = 0
 GMM_FP32 = 1
 
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_nonlinear", "gmm_plan_destroy", "gmm_last_error",
-           "gmm_plan_device_bytes")
+           "gmm_plan_device_bytes", "gmm_profile_enable", "gmm_profile_read")
+PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close")
 
 
 class gmm_params(ctypes.Structure):
@@ -74,6 +75,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_last_error.restype = ctypes.c_char_p
     lib.gmm_plan_device_bytes.argtypes = [vp]
     lib.gmm_plan_device_bytes.restype = ctypes.c_longlong
+    lib.gmm_profile_enable.argtypes = [vp, ci]
+    lib.gmm_profile_enable.restype = ci
+    lib.gmm_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_longlong), ci]
+    lib.gmm_profile_read.restype = ci
     _lib = lib
     return lib
 
@@ -170,6 +175,18 @@ class Plan:
         _check(self.lib.gmm_nonlinear(self.handle, ctypes.c_void_p(At.data_ptr()), int(At.shape[0]),
                                       ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def profile(self, on: bool = True):
+        """Start (and zero) or stop per-kernel HIP-event timing inside the library."""
+        _check(self.lib.gmm_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self) -> dict:
+        """{kernel kind: (total ms, launches)} for launches that did work."""
+        k = len(PROFILE_KINDS)
+        ms = (ctypes.c_double * k)()
+        n = (ctypes.c_longlong * k)()
+        _check(self.lib.gmm_profile_read(self.handle, ms, n, k))
+        return {name: (ms[i], n[i]) for i, name in enumerate(PROFILE_KINDS)}
 
     def device_bytes(self) -> int:
         return int(self.lib.gmm_plan_device_bytes(self.handle))
