@@ -1,9 +1,10 @@
 // Block-wide complex FFT for one row of length N = 2^LOGN (8 <= LOGN <= 15).
 //
-// Design (gfx950): one workgroup owns one row.  Each thread keeps R = 16 (or 32
-// for 2^15) points in registers, does a radix-R butterfly per pass entirely in
+// Design (gfx950): one workgroup owns one row.  Each thread keeps R = 32 points
+// (FP32 rows of 2^10 and more; 16 otherwise) in registers, does a radix-R butterfly per pass entirely in
 // registers, and the passes exchange data through LDS in Stockham (self-
-// sorting) order, so no bit-reversal pass is ever needed.  Real and imaginary
+// sorting) order, so no bit-reversal pass is ever needed.  An FP32 2^14 row
+// takes three passes [32, 16, 32] and two LDS exchanges.  Real and imaginary
 // parts travel through LDS separately (N scalars + 1/16 padding), which keeps
 // an FP64 2^14 row inside the 160 KB LDS and lets two FP32 rows share a CU.
 //
@@ -20,11 +21,13 @@
 
 namespace gmm {
 
-template <int LOGN_>
+template <int LOGN_, int ELEM_BYTES>
 struct FftShape {
   static constexpr int LOGN = LOGN_;
   static constexpr int N = 1 << LOGN;
-  static constexpr int LOGR = (LOGN >= 15) ? 5 : 4;
+  // 32 points per thread for FP32 rows of 2^10 and more; 16 for FP64 rows
+  // (32 complex doubles would need 128 VGPRs for the data alone).
+  static constexpr int LOGR = (ELEM_BYTES == 4 && LOGN >= 10) ? 5 : 4;
   static constexpr int R = 1 << LOGR;
   static constexpr int THREADS = N / R;
   static constexpr int NFULL = LOGN / LOGR;
@@ -113,11 +116,25 @@ __device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], int tid, co
   for (int b = 0; b < B; ++b) {
     const int j = tid + b * S::THREADS;
     if constexpr (NS > 1) {
+      // W^(q k), W = exp(SIGN 2 pi i / (Ns P)): table entries W^(2^e k), e < LP,
+      // multiplied along the set bits of q (at most LP - 1 products).
       const int k = j & (NS - 1);
+      cplx<T> wp[LP];
+#pragma unroll
+      for (int e = 0; e < LP; ++e) {
+        wp[e] = tw[(k << e) << (S::LOGN - LNS - LP)];  // table holds exp(-2 pi i m / N)
+        if (SIGN > 0) wp[e].im = -wp[e].im;
+      }
 #pragma unroll
       for (int q = 1; q < P; ++q) {
-        cplx<T> w = tw[(q * k) << (S::LOGN - LNS - LP)];  // table holds exp(-2 pi i m / N)
-        if (SIGN > 0) w.im = -w.im;
+        cplx<T> w = {T(1), T(0)};
+        bool first = true;
+#pragma unroll
+        for (int e = 0; e < LP; ++e)
+          if (q & (1 << e)) {
+            w = first ? wp[e] : cmul(w, wp[e]);
+            first = false;
+          }
         v[b * P + q] = cmul(v[b * P + q], w);
       }
     }

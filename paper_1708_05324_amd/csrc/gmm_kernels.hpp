@@ -32,9 +32,9 @@ __device__ __forceinline__ double disp_phase(const double* __restrict__ coef, in
 // ---------------------------------------------------------------------------
 // Plain row transform: out = scale * FFT_SIGN(in), one row per block.
 template <typename T, int LOGN, int SIGN>
-__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_fft_rows(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_fft_rows(
     const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, T scale, const cplx<T>* __restrict__ tw) {
-  using S = FftShape<LOGN>;
+  using S = FftShape<LOGN, (int)sizeof(T)>;
   __shared__ T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const size_t row = (size_t)blockIdx.x * S::N;
@@ -51,10 +51,10 @@ __global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_fft_rows(
 // grid (N, count); psi row (jj, p) at psi + (jj * psi_jrows + p) * Nt, where
 // psi_jrows is a row count: N for one field per sub-step, 0 to reuse psi_0.
 template <typename T, int LOGN>
-__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_phase_to_time(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
     const cplx<T>* __restrict__ psi, long psi_jrows, cplx<T>* __restrict__ A, const double* __restrict__ coef,
     int nb, int j0, double dz, double domega, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN>;
+  using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
@@ -77,15 +77,17 @@ __global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_phase_to_time(
 // ---------------------------------------------------------------------------
 // a2 + a3: pair products and Raman convolution.  For pairs Q = (m, n), m <= n:
 //   B_Q(t)  = Re(A_m A_n^*)
-//   B'_Q(t) = (1 - fR) B_Q + fR (h_R * B_Q)(t)
-// Two real rows travel as one complex row z = B_Q1 + i B_Q2; h_R is real, so
-// FFT_{-}(Hs * FFT_{+}(z)) = (h*B_Q1) + i (h*B_Q2) exactly.  Hs = H / Nt.
-// grid (ceil(Np / 2), count).
+//   B'_Q(t) = (1 - fR) B_Q + fR (h_R * B_Q)(t)  =  (g * B_Q)(t)
+// with the blended filter G = (1 - fR) + fR H in the spectrum (the blend is
+// linear, so it is applied as one multiplication).  Two real rows travel as one
+// complex row z = B_Q1 + i B_Q2; G is the transform of a real kernel, so
+// FFT_{-}(Gs * FFT_{+}(z)) = (g*B_Q1) + i (g*B_Q2) exactly.  Gs = G / Nt.
+// grid (ceil(Np / 2), count).  Without Raman (fR = 0) B' = B.
 template <typename T, int LOGN, bool RAMAN>
-__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_pairs(
-    const cplx<T>* __restrict__ A, T* __restrict__ Bp, const int2* __restrict__ pairs, int N, int Np, T wk, T wr,
-    const cplx<T>* __restrict__ Hs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN>;
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_pairs(
+    const cplx<T>* __restrict__ A, T* __restrict__ Bp, const int2* __restrict__ pairs, int N, int Np,
+    const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
   const int tid = threadIdx.x, jj = blockIdx.y;
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_pairs(
   const bool has2 = Q2 < Np;
   const int2 a = pairs[Q1];
   const int2 b = has2 ? pairs[Q2] : a;
+  const bool share = b.x == a.x;  // consecutive pairs usually share their first mode
   const cplx<T>* Aj = A + (size_t)jj * N * S::N;
   const cplx<T>* am = Aj + (size_t)a.x * S::N;
   const cplx<T>* an = Aj + (size_t)a.y * S::N;
@@ -102,38 +105,27 @@ __global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_pairs(
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int t = tid + i * S::THREADS;
-    cplx<T> x = am[t], y = an[t];
-    T b1 = x.re * y.re + x.im * y.im;
+    const cplx<T> x = am[t], y = an[t];
     T b2 = 0;
     if (has2) {
-      cplx<T> u = bm[t], w = bn[t];
+      const cplx<T> u = share ? x : bm[t], w = bn[t];
       b2 = u.re * w.re + u.im * w.im;
     }
-    z[i] = {b1, b2};
+    z[i] = {x.re * y.re + x.im * y.im, b2};
+  }
+  if constexpr (RAMAN) {
+    block_fft<S, T, +1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gs[tid + i * S::THREADS]);
+    block_fft<S, T, -1>(z, lds, tid, tw);
   }
   T* o1 = Bp + ((size_t)jj * Np + Q1) * S::N;
   T* o2 = o1 + S::N;
-  if constexpr (RAMAN) {
-    cplx<T> z0[S::R];
 #pragma unroll
-    for (int i = 0; i < S::R; ++i) z0[i] = z[i];
-    block_fft<S, T, +1>(z, lds, tid, tw);
-#pragma unroll
-    for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Hs[tid + i * S::THREADS]);
-    block_fft<S, T, -1>(z, lds, tid, tw);
-#pragma unroll
-    for (int i = 0; i < S::R; ++i) {
-      const int t = tid + i * S::THREADS;
-      o1[t] = wk * z0[i].re + wr * z[i].re;
-      if (has2) o2[t] = wk * z0[i].im + wr * z[i].im;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < S::R; ++i) {
-      const int t = tid + i * S::THREADS;
-      o1[t] = z[i].re;
-      if (has2) o2[t] = z[i].im;
-    }
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    o1[t] = z[i].re;
+    if (has2) o2[t] = z[i].im;
   }
 }
 
@@ -258,10 +250,10 @@ __global__ __launch_bounds__(256) void k_contract(
 // a6: I_j(w) = exp(-D_w z_j) * i gamma^ (1 + s w/w0) * F{NL_j}(w),
 // F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt.  grid (N, count); in may alias out.
 template <typename T, int LOGN>
-__global__ __launch_bounds__(FftShape<LOGN>::THREADS) void k_spectral_out(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_spectral_out(
     const cplx<T>* in, cplx<T>* out, const double* __restrict__ coef, int nb, int j0, double dz, double domega,
     double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN>;
+  using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
@@ -369,17 +361,18 @@ __global__ __launch_bounds__(256) void k_spec_sums(const cplx<T>* __restrict__ A
   }
 }
 
-// Raman spectral response: Hs[k] = H[k] / H[0] / Nt from H = FFT_{+}(normalised samples).
+// Blended Raman filter: Gs[k] = ((1 - fR) + fR H[k] / H[0]) / Nt, with
+// H = FFT_{+}(normalised samples of h_R).
 template <typename T>
-__global__ __launch_bounds__(256) void k_finish_H(const cplx<double>* __restrict__ H, cplx<T>* __restrict__ Hs,
-                                                  int nt) {
+__global__ __launch_bounds__(256) void k_finish_H(const cplx<double>* __restrict__ H, cplx<T>* __restrict__ Gs,
+                                                  int nt, double fR) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= nt) return;
   const cplx<double> h0 = H[0];
   const double den = h0.re * h0.re + h0.im * h0.im;
   const cplx<double> x = H[k];
   const double re = (x.re * h0.re + x.im * h0.im) / den, im = (x.im * h0.re - x.re * h0.im) / den;
-  Hs[k] = cplx<T>{(T)(re / nt), (T)(im / nt)};
+  Gs[k] = cplx<T>{(T)(((1.0 - fR) + fR * re) / nt), (T)(fR * im / nt)};
 }
 
 }  // namespace gmm

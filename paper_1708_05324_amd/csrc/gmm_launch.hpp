@@ -18,8 +18,7 @@ struct Launch {
                                   int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
                                   const Ctrl* ctrl, hipStream_t s);
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
-                          int count, T wk, T wr, const cplx<T>* Hs, const cplx<T>* tw, const Ctrl* ctrl,
-                          hipStream_t s);
+                          int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
                              int Nt, int count, const Ctrl* ctrl, hipStream_t s);
   static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
@@ -31,7 +30,7 @@ struct Launch {
                           double domega, hipStream_t s);
   static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
                               hipStream_t s);
-  static hipError_t finish_H(const cplx<double>* H, cplx<T>* Hs, int nt, hipStream_t s);
+  static hipError_t finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s);
 };
 
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,

@@ -8,19 +8,19 @@ namespace gmm {
 template <typename T>
 constexpr int max_logn() { return sizeof(T) == 8 ? 14 : 15; }
 
-#define GMM_LOGN_SWITCH(logn, BODY)                   \
+#define GMM_LOGN_SWITCH(logn, ...)                    \
   switch (logn) {                                     \
-    case 8: { constexpr int LOGN = 8; BODY; } break;   \
-    case 9: { constexpr int LOGN = 9; BODY; } break;   \
-    case 10: { constexpr int LOGN = 10; BODY; } break; \
-    case 11: { constexpr int LOGN = 11; BODY; } break; \
-    case 12: { constexpr int LOGN = 12; BODY; } break; \
-    case 13: { constexpr int LOGN = 13; BODY; } break; \
-    case 14: { constexpr int LOGN = 14; BODY; } break; \
+    case 8: { constexpr int LOGN = 8; __VA_ARGS__; } break;   \
+    case 9: { constexpr int LOGN = 9; __VA_ARGS__; } break;   \
+    case 10: { constexpr int LOGN = 10; __VA_ARGS__; } break; \
+    case 11: { constexpr int LOGN = 11; __VA_ARGS__; } break; \
+    case 12: { constexpr int LOGN = 12; __VA_ARGS__; } break; \
+    case 13: { constexpr int LOGN = 13; __VA_ARGS__; } break; \
+    case 14: { constexpr int LOGN = 14; __VA_ARGS__; } break; \
     case 15: {                                         \
       if constexpr (max_logn<T>() >= 15) {             \
         constexpr int LOGN = max_logn<T>();            \
-        BODY;                                          \
+        __VA_ARGS__;                                   \
       } else {                                         \
         return hipErrorInvalidValue;                   \
       }                                                \
@@ -37,7 +37,7 @@ template <typename T>
 hipError_t Launch<T>::fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* out, T scale, int rows,
                                const cplx<T>* tw, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN>;
+    using S = FftShape<LOGN, (int)sizeof(T)>;
     if (sign < 0)
       hipLaunchKernelGGL((k_fft_rows<T, LOGN, -1>), dim3(rows), dim3(S::THREADS), 0, s, in, out, scale, tw);
     else
@@ -51,7 +51,7 @@ hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows
                                     int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
                                     const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN>;
+    using S = FftShape<LOGN, (int)sizeof(T)>;
     hipLaunchKernelGGL((k_phase_to_time<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, psi, psi_jrows, A,
                        coef, nb, j0, dz, domega, tw, ctrl);
   });
@@ -60,17 +60,14 @@ hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows
 
 template <typename T>
 hipError_t Launch<T>::pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
-                            int count, T wk, T wr, const cplx<T>* Hs, const cplx<T>* tw, const Ctrl* ctrl,
-                            hipStream_t s) {
+                            int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN>;
+    using S = FftShape<LOGN, (int)sizeof(T)>;
     dim3 grid((Np + 1) / 2, count);
     if (raman)
-      hipLaunchKernelGGL((k_pairs<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, wk, wr, Hs,
-                         tw, ctrl);
+      hipLaunchKernelGGL((k_pairs<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, Gs, tw, ctrl);
     else
-      hipLaunchKernelGGL((k_pairs<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, wk, wr, Hs,
-                         tw, ctrl);
+      hipLaunchKernelGGL((k_pairs<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, Gs, tw, ctrl);
   });
   return hipGetLastError();
 }
@@ -106,7 +103,7 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
                                    int count, int j0, double dz, double domega, double gscale, double inv_omega0,
                                    int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN>;
+    using S = FftShape<LOGN, (int)sizeof(T)>;
     hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, coef, nb, j0,
                        dz, domega, gscale, inv_omega0, shock, tw, ctrl);
   });
@@ -137,8 +134,8 @@ hipError_t Launch<T>::spec_sums(const cplx<T>* At, int nt, long nn, double domeg
 }
 
 template <typename T>
-hipError_t Launch<T>::finish_H(const cplx<double>* H, cplx<T>* Hs, int nt, hipStream_t s) {
-  hipLaunchKernelGGL((k_finish_H<T>), dim3((nt + 255) / 256), dim3(256), 0, s, H, Hs, nt);
+hipError_t Launch<T>::finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s) {
+  hipLaunchKernelGGL((k_finish_H<T>), dim3((nt + 255) / 256), dim3(256), 0, s, H, Gs, nt, fR);
   return hipGetLastError();
 }
 

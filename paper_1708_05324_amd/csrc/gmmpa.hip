@@ -139,7 +139,7 @@ struct gmm_plan_s {
   // constants
   double* coef = nullptr;  // [N][nb] beta_n / n!
   void* tw = nullptr;      // [nt] exp(-2 pi i m/nt) in field precision
-  void* Hs = nullptr;      // [nt] H / H0 / nt (Raman)
+  void* Hs = nullptr;      // [nt] ((1 - fR) + fR H / H0) / nt (blended Raman filter)
   void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
@@ -216,7 +216,7 @@ struct Runner {
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                      tw(), ctrl, P->stream));
     GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
-                             (T)(1.0 - P->prm.fR), (T)P->prm.fR, (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
+                             (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
     GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N, P->Np, P->nt, count, ctrl,
                                 P->stream));
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
@@ -383,7 +383,7 @@ int build_raman(gmm_plan_s* P, const double* hR) {
   for (int k = 0; k < n; ++k) h[k] = cplx<double>{a[k].real(), a[k].imag()};
   GMM_HIP(hipMemcpy(dH, h.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
   if ((rc = dev_alloc(&P->const_bytes, (cplx<T>**)&P->Hs, n * sizeof(cplx<T>)))) return rc;
-  GMM_HIP(Launch<T>::finish_H(dH, (cplx<T>*)P->Hs, n, P->stream));
+  GMM_HIP(Launch<T>::finish_H(dH, (cplx<T>*)P->Hs, n, P->prm.fR, P->stream));
   GMM_HIP(hipStreamSynchronize(P->stream));
   (void)hipFree(dH);
   P->const_bytes -= (long long)(n * sizeof(cplx<double>));
