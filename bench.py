@@ -28,11 +28,15 @@ PEAKS = {  # MI355X published dense peaks
     "hbm_GBps": 8000.0,
     "mfma_fp32_TFLOPs": 157.3,
     "mfma_fp64_TFLOPs": 78.6,
+    "mfma_bf16_TFLOPs": 2500.0,
+    # three bf16 products per useful multiply-add: useful-work peak of the split contraction
+    "mfma_bf16x3_TFLOPs": 2500.0 / 3.0,
     # vector ALU with packed FP32 disabled: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
     "alu_fp32_TFLOPs": 78.6,
     "alu_fp64_TFLOPs": 78.6,
 }
-TOL = {"fp64": 1e-12, "fp32": 1e-6}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}
 
 
 def work_per_eval(kind: str, N: int, Nt: int, prec: str) -> dict:
@@ -42,6 +46,7 @@ def work_per_eval(kind: str, N: int, Nt: int, prec: str) -> dict:
     cs = 2 * rs
     fft = 5.0 * Nt * math.log2(Nt)
     if kind == "contract":
+        # bf16x3 executes three bf16 products per useful multiply-add; the useful (packed) count is reported
         return {"bound": "mfma", "flops": 2.0 * Np * Np * Nt, "bytes": Np * Nt * rs + 2 * N * Nt * cs}
     if kind == "pairs_raman":
         return {"bound": "alu", "flops": math.ceil(Np / 2) * 2 * fft, "bytes": N * Nt * cs + Np * Nt * rs}
@@ -79,16 +84,25 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     dtype = torch.complex128 if prec == "fp64" else torch.complex64
     A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
     Ls = w.M * w.dz
-    if warmup > 0:
-        A = plan.propagate(A, warmup * Ls, w.dz, w.M).field
-    if profile:
-        plan.profile(True)
+    breakdown, dominant = None, None
+    if warmup > 0:                    # first large step: code loading, allocation, cold caches
+        A = plan.propagate(A, Ls, w.dz, w.M).field
+    if warmup > 1:                    # rest of the warm-up with every kernel kind timed: per-kernel breakdown
+        if profile:
+            plan.profile(True)
+        wres = plan.propagate(A, (warmup - 1) * Ls, w.dz, w.M)
+        A = wres.field
+        if profile:
+            breakdown = {k: (v[0] / wres.stats["large_steps"], v[1]) for k, v in plan.profile_read().items()}
+            dominant = max(breakdown, key=lambda k: breakdown[k][0])
+    # timed region: events only around the dominant kernel kind (two per launch)
+    plan.profile([dominant] if dominant else False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = plan.propagate(A, steps * Ls, w.dz, w.M)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = plan.profile_read() if profile else None
+    prof = {dominant: plan.profile_read()[dominant]} if dominant else None
     plan.profile(False)
     lat = []
     solve_L = 11 * Ls                      # one "solve": 110 small steps (about 1 mm)
@@ -109,6 +123,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
         "nonconverged_steps": st["nonconverged_steps"],
         "stats": st,
         "prof": prof,
+        "breakdown": breakdown,
     }
     if lat:
         lat.sort()
@@ -128,7 +143,8 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str)
     sec = total_ms * 1e-3
     if wk["bound"] == "mfma":
         achieved = wk["flops"] * evals / sec / 1e12
-        peak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else "mfma_fp32_TFLOPs"]
+        peak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else
+                     "mfma_bf16x3_TFLOPs" if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
         unit = "TFLOP/s"
     elif wk["bound"] == "alu":
         achieved = wk["flops"] * evals / sec / 1e12
@@ -173,9 +189,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40, help="timed large steps")
-    ap.add_argument("--warmup", type=int, default=3, help="untimed large steps")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--warmup", type=int, default=4, help="untimed large steps (per-kernel breakdown taken here)")
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs in the other precisions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=20)
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
@@ -199,12 +215,14 @@ def main():
     main_run = run_gpu(args.precision, w, args.steps, args.warmup, args.latency_solves, not args.no_profile)
     extra = {}
     if not args.no_compare:
-        other = "fp64" if args.precision == "fp32" else "fp32"
-        o = run_gpu(other, w, max(4, args.steps // 4), 1, 0, False)
-        extra[other] = {"small_steps_per_s": round(o["small_steps_per_s"], 2),
-                        "evaluations_per_s": round(o["evaluations_per_s"], 2),
-                        "iterations_per_large_step": round(o["iterations_per_large_step"], 3),
-                        "ms_per_large_step": round(o["ms_per_large_step"], 4)}
+        for other in ("bf16x3", "fp32", "fp64"):
+            if other == args.precision:
+                continue
+            o = run_gpu(other, w, max(8, args.steps // 2), 1, 0, False)
+            extra[other] = {"small_steps_per_s": round(o["small_steps_per_s"], 2),
+                            "evaluations_per_s": round(o["evaluations_per_s"], 2),
+                            "iterations_per_large_step": round(o["iterations_per_large_step"], 3),
+                            "ms_per_large_step": round(o["ms_per_large_step"], 4), "tol": TOL[other]}
     line = {
         "metric": "MPA steps/s at N=15 modes, Nt=2^14 (BF16/FP32 vs FP64); p50/p99 solve latency",
         "value": round(main_run["small_steps_per_s"], 2),
@@ -216,7 +234,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "n_modes": N, "nt": Nt, "window_ps": round(Nt * w.dt * 1e12, 3),
                    "M": w.M, "dz_um": round(w.dz * 1e6, 4), "tol": TOL[args.precision], "fR": w.fR,
@@ -231,8 +249,8 @@ def main():
     }
     if main_run["prof"]:
         line["roofline"] = roofline(main_run["prof"], main_run["stats"], N, Nt, args.precision, workload)
-        line["kernel_ms_per_large_step"] = {k: round(v[0] / main_run["stats"]["large_steps"], 4)
-                                            for k, v in main_run["prof"].items()}
+    if main_run["breakdown"]:
+        line["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in main_run["breakdown"].items()}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

@@ -19,7 +19,7 @@
  *
  * Fields cross the boundary as device buffers of interleaved complex numbers,
  * mode-major: element (p, k) at index p*Nt + k.  The element type is complex
- * double for GMM_FP64 plans and complex float for GMM_FP32 plans.
+ * double for GMM_FP64 plans and complex float for GMM_FP32 and GMM_BF16X3 plans.
  *
  * Return codes: 0 success; GMM_NOT_CONVERGED (+1) the propagation completed
  * but at least one large step stopped at max_iter without reaching tol (the
@@ -47,7 +47,9 @@ typedef struct gmm_plan_s* gmm_plan;
 
 typedef enum {
   GMM_FP64 = 0,   /* complex128 fields, FP64 transforms, FP64 MFMA contraction */
-  GMM_FP32 = 1    /* complex64 fields, FP32 transforms, FP32 MFMA contraction */
+  GMM_FP32 = 1,   /* complex64 fields, FP32 transforms, FP32 MFMA contraction */
+  GMM_BF16X3 = 2  /* complex64 fields, FP32 transforms; contraction as S^hi B^hi + S^hi B^lo + S^lo B^hi
+                     with bf16 hi/lo splits on MFMA, FP32 accumulation (up to 15 modes) */
 } gmm_precision;
 
 typedef struct {
@@ -139,9 +141,11 @@ long long gmm_plan_device_bytes(gmm_plan plan);
 
 /*
  * Per-kernel timing with HIP events on the plan's stream (for benchmarks).
- * gmm_profile_enable(plan, 1) clears the totals and brackets every later
- * kernel launch with two events; launches of queued iterations that exit at
- * once (the large step had already converged) are not counted.
+ * gmm_profile_enable(plan, kinds) clears the totals and brackets every later
+ * launch of the kernel kinds whose bit (1 << GMM_PROF_*) is set in `kinds`
+ * with two events (0 turns timing off; GMM_PROF_ALL times every kind).
+ * Launches of queued iterations that exit at once (the large step had
+ * already converged) are not counted.
  * gmm_profile_read copies, for the first n_kinds kernel kinds below, the
  * summed duration in ms and the number of counted launches.
  */
@@ -153,7 +157,8 @@ long long gmm_plan_device_bytes(gmm_plan plan);
 #define GMM_PROF_NORM 5     /* norm reduction + stop decision */
 #define GMM_PROF_CLOSE 6    /* large-step close */
 #define GMM_PROF_KINDS 7
-int gmm_profile_enable(gmm_plan plan, int on);
+#define GMM_PROF_ALL ((1 << GMM_PROF_KINDS) - 1)
+int gmm_profile_enable(gmm_plan plan, int kinds);
 int gmm_profile_read(gmm_plan plan, double* total_ms, long long* launches, int n_kinds);
 
 #ifdef __cplusplus

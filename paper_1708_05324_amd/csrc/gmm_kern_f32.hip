@@ -1,3 +1,61 @@
 // FP32 (complex64 field) instantiation of the propagation kernels.
 #include "gmm_launch_impl.hpp"
 template struct gmm::Launch<float>;
+
+namespace gmm {
+
+hipError_t launch_pairs_bf16(int logn, bool raman, const cplx<float>* A, uint32_t* Bhi, uint32_t* Blo,
+                             const int2* pairs, int N, int Np, int count, const cplx<float>* Gs,
+                             const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
+  using T = float;
+  constexpr int KB = kBf16Kpad / 8;
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, 4>;
+    const int total = (Np + 1) / 2 * count;
+    dim3 grid(8 * ((total + 7) / 8));
+    if (raman)
+      hipLaunchKernelGGL((k_pairs_bf16<LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bhi, Blo, pairs, N, Np, count,
+                         KB, Gs, tw, ctrl);
+    else
+      hipLaunchKernelGGL((k_pairs_bf16<LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bhi, Blo, pairs, N, Np,
+                         count, KB, Gs, tw, ctrl);
+  });
+  return hipGetLastError();
+}
+
+template <int RT>
+static int contract_bf16_blocks() {
+  static int blocks = 0;
+  if (blocks == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_bf16<RT>, 256,
+                                                     ContractBf16Shape<RT>::lds_bytes()) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    blocks = per_cu * cus;
+  }
+  return blocks;
+}
+
+hipError_t launch_contract_bf16(int rt, const void* Shi, const void* Slo, const uint32_t* Bhi, const uint32_t* Blo,
+                                cplx<float>* A_NL, const int* pidx, int N, int Nt, int count, const Ctrl* ctrl,
+                                hipStream_t s) {
+  const int ntiles = count * (Nt / 64);
+#define GMM_BF_CASE(R)                                                                                            \
+  if (rt == R) {                                                                                                  \
+    const int nb = std::min(ntiles, contract_bf16_blocks<R>());                                                   \
+    hipLaunchKernelGGL((k_contract_bf16<R>), dim3(nb), dim3(256), ContractBf16Shape<R>::lds_bytes(), s,          \
+                       (const uint4*)Shi, (const uint4*)Slo, (const uint4*)Bhi, (const uint4*)Blo, A_NL, pidx, N, \
+                       Nt, ntiles, ctrl);                                                                         \
+    return hipGetLastError();                                                                                     \
+  }
+  GMM_BF_CASE(1)
+  GMM_BF_CASE(2)
+#undef GMM_BF_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gmm

@@ -16,6 +16,24 @@ namespace gmm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Workgroups are dealt to the 8 XCDs round-robin by id.  For a 1-D grid of
+// 8 * G blocks, block b runs on XCD b % 8; numbering work items
+// (b % 8) * G + b / 8 gives each XCD a contiguous range, so neighbouring work
+// items share that XCD's L2.  Returns -1 for padding blocks.
+__device__ __forceinline__ int xcd_local_index(int b, int G, int total) {
+  const int w = (b & 7) * G + (b >> 3);
+  return w < total ? w : -1;
+}
 
 __device__ __forceinline__ bool skip_iteration(const Ctrl* c) {
   return c != nullptr && *(volatile const int*)&c->done != 0;
@@ -82,16 +100,20 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
 // linear, so it is applied as one multiplication).  Two real rows travel as one
 // complex row z = B_Q1 + i B_Q2; G is the transform of a real kernel, so
 // FFT_{-}(Gs * FFT_{+}(z)) = (g*B_Q1) + i (g*B_Q2) exactly.  Gs = G / Nt.
-// grid (ceil(Np / 2), count).  Without Raman (fR = 0) B' = B.
+// 1-D grid of 8 ceil(ceil(Np/2) count / 8) blocks in XCD-local order (the pair
+// blocks of one sub-step share an L2).  Without Raman (fR = 0) B' = B.
 template <typename T, int LOGN, bool RAMAN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_pairs(
-    const cplx<T>* __restrict__ A, T* __restrict__ Bp, const int2* __restrict__ pairs, int N, int Np,
+    const cplx<T>* __restrict__ A, T* __restrict__ Bp, const int2* __restrict__ pairs, int N, int Np, int count,
     const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
-  const int tid = threadIdx.x, jj = blockIdx.y;
-  const int Q1 = 2 * blockIdx.x, Q2 = Q1 + 1;
+  const int PB = (Np + 1) / 2;  // pair blocks per sub-step; 1-D grid of 8 G blocks
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x, jj = w / PB;
+  const int Q1 = 2 * (w - jj * PB), Q2 = Q1 + 1;
   const bool has2 = Q2 < Np;
   const int2 a = pairs[Q1];
   const int2 b = has2 ? pairs[Q2] : a;
@@ -126,6 +148,65 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
     const int t = tid + i * S::THREADS;
     o1[t] = z[i].re;
     if (has2) o2[t] = z[i].im;
+  }
+}
+
+// Same pair products and Raman convolution, written for the BF16 split
+// contraction: x = hi + lo with hi = bf16(x), lo = bf16(x - hi), in two planes
+// laid out [count][Kpad/8][Nt][8] (eight consecutive pairs contiguous for each
+// time sample, one 16-byte MFMA operand).  The two pairs of a block are
+// neighbours in one group of eight, so each plane gets one 32-bit store per
+// sample.  Pair slots Np..Kpad-1 are never written (zero from allocation).
+template <int LOGN, bool RAMAN>
+__global__ __launch_bounds__((FftShape<LOGN, 4>::THREADS)) void k_pairs_bf16(
+    const cplx<float>* __restrict__ A, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo,
+    const int2* __restrict__ pairs, int N, int Np, int count, int KB, const cplx<float>* __restrict__ Gs,
+    const cplx<float>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, 4>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ float lds[RAMAN ? S::LDS_ELEMS : 1];
+  const int PB = (Np + 1) / 2;  // pair blocks per sub-step; 1-D grid of 8 G blocks
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x, jj = w / PB;
+  const int Q1 = 2 * (w - jj * PB), Q2 = Q1 + 1;
+  const bool has2 = Q2 < Np;
+  const int2 a = pairs[Q1];
+  const int2 b = has2 ? pairs[Q2] : a;
+  const bool share = b.x == a.x;
+  const cplx<float>* Aj = A + (size_t)jj * N * S::N;
+  const cplx<float>* am = Aj + (size_t)a.x * S::N;
+  const cplx<float>* an = Aj + (size_t)a.y * S::N;
+  const cplx<float>* bm = Aj + (size_t)b.x * S::N;
+  const cplx<float>* bn = Aj + (size_t)b.y * S::N;
+  cplx<float> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    const cplx<float> x = am[t], y = an[t];
+    float b2 = 0.f;
+    if (has2) {
+      const cplx<float> u = share ? x : bm[t], w = bn[t];
+      b2 = u.re * w.re + u.im * w.im;
+    }
+    z[i] = {x.re * y.re + x.im * y.im, b2};
+  }
+  if constexpr (RAMAN) {
+    block_fft<S, float, +1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gs[tid + i * S::THREADS]);
+    block_fft<S, float, -1>(z, lds, tid, tw);
+  }
+  // 32-bit word index of (group Q1/8, sample t, slots Q1%8 and Q1%8 + 1)
+  const size_t base = (((size_t)jj * KB + (Q1 >> 3)) * S::N) * 4 + ((Q1 & 7) >> 1);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    const uint32_t h1 = bf16_bits(z[i].re), h2 = has2 ? bf16_bits(z[i].im) : 0u;
+    const uint32_t l1 = bf16_bits(z[i].re - bf16_value(h1));
+    const uint32_t l2 = has2 ? bf16_bits(z[i].im - bf16_value(h2)) : 0u;
+    Bhi[base + (size_t)t * 4] = h1 | (h2 << 16);
+    Blo[base + (size_t)t * 4] = l1 | (l2 << 16);
   }
 }
 
@@ -243,6 +324,233 @@ __global__ __launch_bounds__(256) void k_contract(
         s.im += c * a[l].im;
       }
     Aj[(size_t)p * Nt + t0 + lane] = s;
+  }
+}
+
+// Mode projection shared by the persistent contraction kernels.  The A block
+// of a 64-column tile (N rows) is fetched into registers before the products,
+// so its latency hides behind the MFMA work; afterwards it is staged in LDS
+// next to the C tile, and each wave forms NL_p(t) = sum_l C_(p,l)(t) A_l(t) for
+// its modes p = wave, wave + 4, ...  NL overwrites A: the tile belongs to one
+// block and all of its A values are in registers before any store.
+template <typename T, int NMAX>
+struct TileA {
+  static constexpr int PER_THREAD = (NMAX * 64 + 255) / 256;
+  cplx<T> v[PER_THREAD];
+  __device__ __forceinline__ void fetch(const cplx<T>* Aj, int N, int Nt, int t0, int tid) {
+#pragma unroll
+    for (int q = 0; q < PER_THREAD; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < N * 64) v[q] = Aj[(size_t)(idx >> 6) * Nt + t0 + (idx & 63)];
+    }
+  }
+  __device__ __forceinline__ void stage(cplx<T>* sA, int N, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER_THREAD; ++q) {
+      const int idx = tid + q * 256;
+      if (idx < N * 64) sA[idx] = v[q];
+    }
+  }
+};
+
+template <typename T, int NMAX>
+__device__ __forceinline__ void project_modes(const T* sC, const cplx<T>* sA, const int* sP, cplx<T>* Aj, int N,
+                                              int Nt, int t0, int wave, int lane) {
+  for (int p = wave; p < N; p += 4) {
+    cplx<T> sum = {T(0), T(0)};
+#pragma unroll
+    for (int l = 0; l < NMAX; ++l)
+      if (l < N) {
+        const T c = sC[sP[p * N + l] * 64 + lane];
+        const cplx<T> a = sA[l * 64 + lane];
+        sum.re += c * a.re;
+        sum.im += c * a.im;
+      }
+    Aj[(size_t)p * Nt + t0 + lane] = sum;
+  }
+}
+
+// Contraction for Rpad <= 128 (N <= 15), persistent over 64-column tiles.
+// Each wave keeps its 16 RT rows of S^ (all K) in registers for the life of
+// the block, so the coupling matrix is read once per block; B' fragments are
+// loaded straight from global memory (the four waves of a block read the same
+// tile, which stays in L1/L2).  Rows k >= Np of S^ are zero, so B' row indices
+// are clamped to Np - 1 instead of branching.
+// LDS: C tile [RPAD][64], A tile [N][64] complex, pair-index table [N][N].
+template <int RT, typename T>
+constexpr size_t contract_reg_lds() {
+  return (size_t)64 * RT * 64 * sizeof(T) + (size_t)ContractShape<RT>::NMAX * 64 * sizeof(cplx<T>) +
+         (size_t)ContractShape<RT>::NMAX * ContractShape<RT>::NMAX * sizeof(int);
+}
+
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void k_contract_reg(
+    const T* __restrict__ ST, const T* __restrict__ Bp, cplx<T>* A_NL, const int* __restrict__ pidx, int N,
+    int Np, int Nt, int ntiles, const Ctrl* ctrl) {
+  using CS = ContractShape<RT>;
+  constexpr int RPAD = CS::RPAD, TN = CS::TN, KS = RPAD / 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sC = reinterpret_cast<T*>(smem_raw);                                // [RPAD][TN]
+  cplx<T>* sA = reinterpret_cast<cplx<T>*>(sC + RPAD * TN);              // [N][TN]
+  int* sP = reinterpret_cast<int*>(sA + CS::NMAX * TN);                  // [N][N]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int i = tid; i < N * N; i += 256) sP[i] = pidx[i];
+  T a[RT][KS];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) a[r][s] = ST[(size_t)(4 * s + lk) * RPAD + wave * 16 * RT + r * 16 + lr];
+  const int tiles_per_j = Nt / TN;
+  TileA<T, CS::NMAX> at;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * TN;
+    const T* Bj = Bp + (size_t)jj * Np * Nt + t0 + lr;
+    cplx<T>* Aj = A_NL + (size_t)jj * N * Nt;
+    at.fetch(Aj, N, Nt, t0, tid);
+    acc_t acc[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = min(4 * s + lk, Np - 1);
+      const T* brow = Bj + (size_t)k * Nt;
+      T b[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = brow[c * 16];
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = Mfma<T>::mma(a[r][s], b[c], acc[r][c]);
+    }
+    __syncthreads();  // the previous tile's projection has finished reading sC and sA
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = wave * 16 * RT + r * 16 + Mfma<T>::out_row(lk, i);
+          sC[row * TN + c * 16 + lr] = acc[r][c][i];
+        }
+    at.stage(sA, N, tid);
+    __syncthreads();
+    project_modes<T, CS::NMAX>(sC, sA, sP, Aj, N, Nt, t0, wave, lane);
+  }
+}
+
+// BF16 split contraction C = S^hi B'hi + S^hi B'lo + S^lo B'hi (FP32 accumulate)
+// on v_mfma_f32_16x16x32_bf16, for Rpad <= 128.  Lane l supplies
+// A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and holds
+// D[4 (l / 16) + i][l % 16] in accumulator register i (measured with a probe).
+// The coupling slices (hi, lo) stay in registers; each 64-column tile of B'
+// (both planes, Kpad x 64 x 2 x 2 bytes) is staged in LDS, and the next tile is
+// fetched into registers while the current one is multiplied.
+template <int RT>
+struct ContractBf16Shape {
+  static constexpr int RPAD = 64 * RT;
+  static constexpr int KPAD = 128;  // K up to 128 pairs (N <= 15)
+  static constexpr int KS = KPAD / 32;
+  static constexpr int KB = KPAD / 8;
+  static constexpr int TN = 64;
+  static constexpr int NMAX = RT == 1 ? 10 : 15;
+  static constexpr int TILE_WORDS4 = 2 * KB * TN;  // 16-byte chunks of one tile (both planes)
+  static constexpr int CHUNKS = TILE_WORDS4 / 256;  // per thread
+  // B tile (aliased by the C tile after the products) + A tile + pair-index table
+  static constexpr size_t lds_bytes() {
+    size_t b = (size_t)TILE_WORDS4 * 16, c = (size_t)RPAD * TN * 4;
+    return (b > c ? b : c) + (size_t)NMAX * TN * 8 + (size_t)NMAX * NMAX * 4;
+  }
+};
+
+template <int RT>
+__global__ __launch_bounds__(256) void k_contract_bf16(
+    const uint4* __restrict__ Shi, const uint4* __restrict__ Slo, const uint4* __restrict__ Bhi,
+    const uint4* __restrict__ Blo, cplx<float>* A_NL, const int* __restrict__ pidx, int N, int Nt, int ntiles,
+    const Ctrl* ctrl) {
+  using CS = ContractBf16Shape<RT>;
+  constexpr int RPAD = CS::RPAD, KS = CS::KS, KB = CS::KB, TN = CS::TN;
+  constexpr size_t BC_BYTES = CS::TILE_WORDS4 * 16 > RPAD * TN * 4 ? CS::TILE_WORDS4 * 16 : RPAD * TN * 4;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint4* sB = reinterpret_cast<uint4*>(smem_raw);                            // [plane][KB][TN] 16-byte chunks
+  float* sC = reinterpret_cast<float*>(smem_raw);                            // [RPAD][TN], after the products
+  cplx<float>* sA = reinterpret_cast<cplx<float>*>(smem_raw + BC_BYTES);     // [N][TN]
+  int* sP = reinterpret_cast<int*>(sA + CS::NMAX * TN);                      // [N][N]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int i = tid; i < N * N; i += 256) sP[i] = pidx[i];
+  // coupling operands: row = 16 RT wave + 16 r + lr, k = 32 s + 8 lk .. + 7  (rows of KPAD bf16 = KB chunks)
+  bf16x8 ah[RT][KS], al[RT][KS];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const size_t idx = (size_t)(wave * 16 * RT + r * 16 + lr) * KB + 4 * s + lk;
+      uint4 h = Shi[idx], l = Slo[idx];
+      ah[r][s] = __builtin_bit_cast(bf16x8, h);
+      al[r][s] = __builtin_bit_cast(bf16x8, l);
+    }
+  const int tiles_per_j = Nt / TN;
+  // chunk c of a tile: plane = c / (KB TN), kb = (c / TN) % KB, t = c % TN
+  uint4 pre[CS::CHUNKS];
+  auto fetch = [&](int tile) {
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * TN;
+#pragma unroll
+    for (int q = 0; q < CS::CHUNKS; ++q) {
+      const int c = tid + q * 256;
+      const int plane = c / (KB * TN), kb = (c / TN) % KB, t = c % TN;
+      const uint4* src = plane ? Blo : Bhi;
+      pre[q] = src[((size_t)jj * KB + kb) * Nt + t0 + t];
+    }
+  };
+  TileA<float, CS::NMAX> at;
+  if ((int)blockIdx.x < ntiles) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * TN;
+    cplx<float>* Aj = A_NL + (size_t)jj * N * Nt;
+    __syncthreads();  // previous tile's projection has finished reading sC and sA
+#pragma unroll
+    for (int q = 0; q < CS::CHUNKS; ++q) sB[tid + q * 256] = pre[q];
+    at.fetch(Aj, N, Nt, t0, tid);
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) fetch(tile + gridDim.x);
+    floatx4 acc[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int off = (4 * s + lk) * TN + c * 16 + lr;
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, sB[off]);
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, sB[KB * TN + off]);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r][s], bh, acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r][s], bl, acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r][s], bh, acc[r][c], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // all waves are done reading sB before sC overwrites it
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sC[(wave * 16 * RT + r * 16 + 4 * lk + i) * TN + c * 16 + lr] = acc[r][c][i];
+    at.stage(sA, N, tid);
+    __syncthreads();
+    project_modes<float, CS::NMAX>(sC, sA, sP, Aj, N, Nt, t0, wave, lane);
   }
 }
 

@@ -33,6 +33,15 @@ struct Launch {
   static hipError_t finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s);
 };
 
+// BF16 split contraction path (complex64 fields, Np <= 128).
+constexpr int kBf16Kpad = 128;
+hipError_t launch_pairs_bf16(int logn, bool raman, const cplx<float>* A, uint32_t* Bhi, uint32_t* Blo,
+                             const int2* pairs, int N, int Np, int count, const cplx<float>* Gs,
+                             const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
+hipError_t launch_contract_bf16(int rt, const void* Shi, const void* Slo, const uint32_t* Bhi, const uint32_t* Blo,
+                                cplx<float>* A_NL, const int* pidx, int N, int Nt, int count, const Ctrl* ctrl,
+                                hipStream_t s);
+
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);

@@ -3,6 +3,8 @@
 #include "gmm_kernels.hpp"
 #include "gmm_launch.hpp"
 
+#include <algorithm>
+
 namespace gmm {
 
 template <typename T>
@@ -63,19 +65,53 @@ hipError_t Launch<T>::pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const
                             int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
     using S = FftShape<LOGN, (int)sizeof(T)>;
-    dim3 grid((Np + 1) / 2, count);
+    const int total = (Np + 1) / 2 * count;
+    dim3 grid(8 * ((total + 7) / 8));
     if (raman)
-      hipLaunchKernelGGL((k_pairs<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, Gs, tw, ctrl);
+      hipLaunchKernelGGL((k_pairs<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, count, Gs, tw,
+                         ctrl);
     else
-      hipLaunchKernelGGL((k_pairs<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, Gs, tw, ctrl);
+      hipLaunchKernelGGL((k_pairs<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bp, pairs, N, Np, count, Gs, tw,
+                         ctrl);
   });
   return hipGetLastError();
+}
+
+template <typename T, int RT>
+int contract_reg_blocks() {
+  static int blocks = 0;
+  if (blocks == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_reg<T, RT>, 256,
+                                                     contract_reg_lds<RT, T>()) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    blocks = per_cu * cus;
+  }
+  return blocks;
 }
 
 template <typename T>
 hipError_t Launch<T>::contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
                                int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
-  dim3 grid(count * (Nt / 64));
+  const int ntiles = count * (Nt / 64);
+  if (rt <= 2) {  // coupling slice resident in registers, persistent blocks
+#define GMM_RT_REG(R)                                                                                        \
+  if (rt == R) {                                                                                             \
+    const int nb = std::min(ntiles, contract_reg_blocks<T, R>());                                            \
+    hipLaunchKernelGGL((k_contract_reg<T, R>), dim3(nb), dim3(256), (contract_reg_lds<R, T>()), s, ST, Bp, A_NL, \
+                       pidx, N, Np, Nt, ntiles, ctrl);                                                       \
+    return hipGetLastError();                                                                                \
+  }
+    GMM_RT_REG(1)
+    GMM_RT_REG(2)
+#undef GMM_RT_REG
+  }
+  dim3 grid(ntiles);
   switch (rt) {
 #define GMM_RT_CASE(R)                                                                                         \
   case R: {                                                                                                    \

@@ -9,9 +9,10 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
-#include "../../include/gmmpa.h"
+#include "gmmpa.h"
 #include "gmm_common.hpp"
 #include "gmm_launch.hpp"
 
@@ -38,14 +39,15 @@ int fail(int code, const std::string& msg) {
 #define GMM_LAUNCH(P, KIND, call)                                                  \
   do {                                                                             \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                         \
-    if ((P)->prof.on) {                                                            \
+    const bool t_ = (P)->prof.on && ((P)->prof.mask >> (KIND) & 1u);               \
+    if (t_) {                                                                      \
       a_ = (P)->prof.get();                                                        \
       b_ = (P)->prof.get();                                                        \
       if (!a_ || !b_) return fail(GMM_ERR_HIP, "hipEventCreate failed");           \
       GMM_HIP(hipEventRecord(a_, (P)->stream));                                    \
     }                                                                              \
     GMM_HIP(call);                                                                 \
-    if ((P)->prof.on) {                                                            \
+    if (t_) {                                                                      \
       GMM_HIP(hipEventRecord(b_, (P)->stream));                                    \
       (P)->prof.recs.push_back({a_, b_, (KIND), (P)->prof.cur_step, (P)->prof.cur_iter}); \
     }                                                                              \
@@ -88,6 +90,7 @@ struct GmmProfiler {
     int kind, step, iter;
   };
   bool on = false;
+  unsigned mask = 0;  // bit k: time kernels of kind k
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   std::vector<int> step_iters;  // iterations that ran, per large step of the current propagate
@@ -134,13 +137,15 @@ struct gmm_plan_s {
   int N = 0, nt = 0, logn = 0, nb = 0, Np = 0, rt = 0, rpad = 0;
   hipStream_t stream = nullptr;
   double domega = 0, gamma_hat = 0;
-  bool fp64 = true, raman = false;
+  bool fp64 = true, raman = false, bf16 = false;
   size_t esz = 0;  // bytes per real of the field precision
   // constants
   double* coef = nullptr;  // [N][nb] beta_n / n!
   void* tw = nullptr;      // [nt] exp(-2 pi i m/nt) in field precision
   void* Hs = nullptr;      // [nt] ((1 - fR) + fR H / H0) / nt (blended Raman filter)
-  void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed
+  void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed (FP64 / FP32)
+  void* Shi = nullptr;     // [rpad][128] bf16 high part of the packed matrix, K contiguous (BF16X3)
+  void* Slo = nullptr;     // [rpad][128] bf16 low part
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
   // workspace
@@ -181,6 +186,13 @@ void free_workspace(gmm_plan_s* P) {
 
 size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->esz; }
 
+// B' for `cap` sub-steps: [cap][Np][Nt] reals, or two bf16 planes [cap][Kpad/8][Nt][8].
+size_t bp_bytes(const gmm_plan_s* P, int cap) {
+  if (P->bf16) return 2 * (size_t)cap * gmm::kBf16Kpad * P->nt * 2;
+  return (size_t)cap * P->Np * P->nt * P->esz;
+}
+size_t bp_plane_words(const gmm_plan_s* P) { return (size_t)P->cap * gmm::kBf16Kpad * P->nt / 2; }
+
 int ensure_workspace(gmm_plan_s* P, int cap) {
   if (cap <= P->cap) return GMM_OK;
   const size_t fb = field_bytes(P);
@@ -189,10 +201,16 @@ int ensure_workspace(gmm_plan_s* P, int cap) {
   int rc;
   if ((rc = dev_alloc(c, &P->psi0, fb)) || (rc = dev_alloc(c, &P->I0, fb)) || (rc = dev_alloc(c, &P->psi, fb * cap)) ||
       (rc = dev_alloc(c, &P->work, fb * cap)) ||
-      (rc = dev_alloc(c, &P->Bp, (size_t)cap * P->Np * P->nt * P->esz)) ||
+      (rc = dev_alloc(c, &P->Bp, bp_bytes(P, cap))) ||
       (rc = dev_alloc(c, &P->partials, 2 * sizeof(double) * gmm::trapz_blocks((long)P->N * P->nt)))) {
     free_workspace(P);
     return rc;
+  }
+  if (P->bf16) {  // pair slots beyond Np are read by the contraction and must stay zero
+    if (hipMemset(P->Bp, 0, bp_bytes(P, cap)) != hipSuccess) {
+      free_workspace(P);
+      return fail(GMM_ERR_HIP, "hipMemset of the pair buffer failed");
+    }
   }
   P->cap = cap;
   return GMM_OK;
@@ -215,10 +233,22 @@ struct Runner {
     cplx<T>* W = (cplx<T>*)P->work;
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                      tw(), ctrl, P->stream));
-    GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
-                             (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
-    GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N, P->Np, P->nt, count, ctrl,
-                                P->stream));
+    if constexpr (std::is_same<T, float>::value) {
+      if (P->bf16) {
+        uint32_t* bhi = (uint32_t*)P->Bp;
+        uint32_t* blo = bhi + bp_plane_words(P);
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
+                                                             count, (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, P->Shi, P->Slo, bhi, blo, W, P->pidx, P->N,
+                                                                   P->nt, count, ctrl, P->stream));
+      }
+    }
+    if (!P->bf16) {
+      GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
+                                                     (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N,
+                                                           P->Np, P->nt, count, ctrl, P->stream));
+    }
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                     P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), ctrl,
                                     P->stream));
@@ -366,6 +396,39 @@ int upload_typed(gmm_plan_s* P, const std::vector<double>& ST, const std::vector
   return GMM_OK;
 }
 
+// Host bf16 (round to nearest even) of a float.
+uint16_t host_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float host_bf16_value(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+// hi/lo split of the packed coupling matrix, rows (p,l) with K = 128 contiguous.
+int upload_bf16_split(gmm_plan_s* P, const std::vector<double>& ST) {
+  const int K = gmm::kBf16Kpad;
+  std::vector<uint16_t> hi((size_t)P->rpad * K, 0), lo((size_t)P->rpad * K, 0);
+  for (int r = 0; r < P->rpad; ++r)
+    for (int k = 0; k < P->Np; ++k) {
+      const float x = (float)ST[(size_t)k * P->rpad + r];
+      const uint16_t h = host_bf16(x);
+      hi[(size_t)r * K + k] = h;
+      lo[(size_t)r * K + k] = host_bf16(x - host_bf16_value(h));
+    }
+  int rc;
+  if ((rc = dev_alloc(&P->const_bytes, &P->Shi, hi.size() * 2)) || (rc = dev_alloc(&P->const_bytes, &P->Slo, lo.size() * 2)))
+    return rc;
+  GMM_HIP(hipMemcpy(P->Shi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+  GMM_HIP(hipMemcpy(P->Slo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+  return GMM_OK;
+}
+
 template <typename T>
 int build_raman(gmm_plan_s* P, const double* hR) {
   // weights h_R(k dt) normalised to unit sum; H = FFT_{+}(w); Hs = H / H[0] / Nt
@@ -393,7 +456,7 @@ int build_raman(gmm_plan_s* P, const double* hR) {
 void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
-  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, (void*)P->pidx, (void*)P->pairs, (void*)P->ctrl})
+  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, (void*)P->pidx, (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
   if (P->h_partials) (void)hipHostFree(P->h_partials);
@@ -409,8 +472,10 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (nt < 256 || (nt & (nt - 1))) return fail(GMM_ERR_ARG, "nt must be a power of two >= 256");
   int logn = 0;
   while ((1 << logn) < nt) ++logn;
-  if (p->precision != GMM_FP64 && p->precision != GMM_FP32) return fail(GMM_ERR_ARG, "unknown precision");
+  if (p->precision != GMM_FP64 && p->precision != GMM_FP32 && p->precision != GMM_BF16X3)
+    return fail(GMM_ERR_ARG, "unknown precision");
   const bool fp64 = p->precision == GMM_FP64;
+  const bool bf16 = p->precision == GMM_BF16X3;
   if (fp64 ? !Launch<double>::supports_logn(logn) : !Launch<float>::supports_logn(logn))
     return fail(GMM_ERR_UNSUPPORTED, "nt outside 2^8..2^15 (2^14 for FP64)");
   if (p->n_beta < 1) return fail(GMM_ERR_ARG, "n_beta must be >= 1");
@@ -426,6 +491,8 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   const int rpad = ((Np + 63) / 64) * 64;
   if (rpad > gmm::contract_max_rows())
     return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: packed contraction exceeds 256 rows in this build");
+  if (bf16 && Np > gmm::kBf16Kpad)
+    return fail(GMM_ERR_UNSUPPORTED, "the BF16 split contraction supports up to 15 modes in this build");
   // tensor checks: real, S_plmn = S_plnm = S_lpmn
   const size_t n4 = (size_t)N * N * N * N;
   double smax = 0;
@@ -462,6 +529,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   P->domega = domega;
   P->gamma_hat = p->n2 * p->omega0 / kC;
   P->fp64 = fp64;
+  P->bf16 = bf16;
   P->raman = raman;
   P->esz = fp64 ? 8 : 4;
 
@@ -510,6 +578,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     return bail(fail(GMM_ERR_HIP, "copy of pair tables failed"));
   rc = fp64 ? upload_typed<double>(P, ST, tw) : upload_typed<float>(P, ST, tw);
   if (rc) return bail(rc);
+  if (bf16 && (rc = upload_bf16_split(P, ST))) return bail(rc);
   if (raman) {
     rc = fp64 ? build_raman<double>(P, hR) : build_raman<float>(P, hR);
     if (rc) return bail(rc);
@@ -568,9 +637,10 @@ const char* gmm_last_error(void) { return g_last_error.c_str(); }
 
 long long gmm_plan_device_bytes(gmm_plan plan) { return plan ? plan->const_bytes + plan->ws_bytes : 0; }
 
-int gmm_profile_enable(gmm_plan plan, int on) {
+int gmm_profile_enable(gmm_plan plan, int kinds) {
   if (!plan) return fail(GMM_ERR_ARG, "null plan");
-  plan->prof.on = on != 0;
+  plan->prof.mask = (unsigned)kinds & ((1u << GMM_PROF_KINDS) - 1u);
+  plan->prof.on = plan->prof.mask != 0;
   plan->prof.reset();
   return GMM_OK;
 }

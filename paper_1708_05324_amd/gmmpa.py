@@ -26,6 +26,7 @@ GMM_ERR_UNSUPPORTED = -5
 GMM_ERR_DIVERGED = -6
 GMM_FP64 = 0
 GMM_FP32 = 1
+GMM_BF16X3 = 2
 
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_nonlinear", "gmm_plan_destroy", "gmm_last_error",
            "gmm_plan_device_bytes", "gmm_profile_enable", "gmm_profile_read")
@@ -109,7 +110,8 @@ class Result:
 class Plan:
     """A propagation plan: the inputs of Eq. (1) bound to one GPU stream.
 
-    precision: "fp64" (complex128 fields) or "fp32" (complex64 fields).
+    precision: "fp64" (complex128 fields), "fp32" (complex64 fields) or "bf16x3"
+    (complex64 fields, BF16 hi/lo split contraction with FP32 accumulation).
     """
 
     def __init__(self, betas, SK, hR=None, *, nt: int, dt: float, omega0: float, n2: float, fR: float,
@@ -129,7 +131,7 @@ class Plan:
         self.precision = precision
         self.nt = nt
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
-        prec = {"fp64": GMM_FP64, "fp32": GMM_FP32}[precision]
+        prec = {"fp64": GMM_FP64, "fp32": GMM_FP32, "bf16x3": GMM_BF16X3}[precision]
         self.params = gmm_params(self.n_modes, nt, betas.shape[1], dt, omega0, n2, fR, int(self_steepening),
                                  prec, tol, max_iter, fixed_iters)
         if stream is None:
@@ -176,9 +178,18 @@ class Plan:
                                       ctypes.c_void_p(out.data_ptr())))
         return out
 
-    def profile(self, on: bool = True):
-        """Start (and zero) or stop per-kernel HIP-event timing inside the library."""
-        _check(self.lib.gmm_profile_enable(self.handle, int(bool(on))))
+    def profile(self, kinds=True):
+        """Start (and zero) per-kernel HIP-event timing inside the library for the
+        given kernel kinds (names from PROFILE_KINDS; True = all), or stop it (False)."""
+        if kinds is True:
+            mask = (1 << len(PROFILE_KINDS)) - 1
+        elif not kinds:
+            mask = 0
+        else:
+            mask = 0
+            for k in ([kinds] if isinstance(kinds, str) else kinds):
+                mask |= 1 << PROFILE_KINDS.index(k)
+        _check(self.lib.gmm_profile_enable(self.handle, mask))
 
     def profile_read(self) -> dict:
         """{kernel kind: (total ms, launches)} for launches that did work."""

@@ -89,6 +89,7 @@ def _create(lib, prm, S=None, hR=None, SR=None, betas=None):
     (dict(fR=0.18), gmmpa.GMM_ERR_ARG),                     # Raman without h_R
     (dict(self_steepening=1, dt=0.5e-15), gmmpa.GMM_ERR_ARG),   # 1 + w/w0 <= 0 on the grid
     (dict(n_modes=23, nt=256), gmmpa.GMM_ERR_UNSUPPORTED),  # beyond 256 packed rows
+    (dict(n_modes=16, precision=2), gmmpa.GMM_ERR_UNSUPPORTED),   # BF16 split: up to 15 modes
 ])
 def test_invalid_plans_are_rejected(lib, kw, code):
     rc, h = _create(lib, _params(**kw))

@@ -16,8 +16,8 @@ from paper_1708_05324_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL_OP = {"fp64": 1e-11, "fp32": 2e-5}
-TOL_PROP = {"fp64": 1e-10, "fp32": 1e-5}
+TOL_OP = {"fp64": 1e-11, "fp32": 2e-5, "bf16x3": 1e-4}
+TOL_PROP = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +35,7 @@ def relmax(a, b):
 
 
 def to_dev(torch, x, prec):
-    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    dt = torch.complex128 if prec == "fp64" else torch.complex64   # bf16x3 keeps complex64 fields
     return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt)
 
 
@@ -59,11 +59,13 @@ CASES = [  # (groups, nt, fR, shock, dt)
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_s{c[3]}")
 def test_nonlinear_operator_matches_oracle(torch_gpu, prec, case):
     torch = torch_gpu
     g, nt, fR, s, dt = case
+    if prec == "bf16x3" and g > 5:
+        pytest.skip("the BF16 split contraction covers up to 15 modes")
     w = small_workload(N_groups=g, nt=nt, fR=fR, s=s, dt=dt)
     m = O.model_from_workload(w)
     ops = O._Ops(m, nt)
@@ -101,7 +103,7 @@ def test_linear_propagation_is_exact(torch_gpu, prec):
     assert res.stats["small_steps"] == 20 and res.stats["large_steps"] == 4
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("M,nsteps", [(5, 15), (4, 10)])   # 10 = 2 x 4 + a last large step of 2
 def test_propagation_fixed_iterations_matches_oracle(torch_gpu, prec, M, nsteps):
     torch = torch_gpu
@@ -166,7 +168,7 @@ def metric_reference():
     return w, ref
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_metric_workload_one_large_step(torch_gpu, metric_reference, prec):
     torch = torch_gpu
     w, ref = metric_reference
@@ -177,7 +179,7 @@ def test_metric_workload_one_large_step(torch_gpu, metric_reference, prec):
     assert err < TOL_PROP[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_small_workloads_several_large_steps(torch_gpu, prec, cfg):
     """3 modes / 2^10 (Kerr only, the stated 1 mm step) and 6 modes / 2^13
@@ -186,11 +188,11 @@ def test_small_workloads_several_large_steps(torch_gpu, prec, cfg):
     w = synth.config1() if cfg == 1 else synth.config2()
     m = O.model_from_workload(w)
     L = 3 * w.M * w.dz
-    tol = 1e-9 if prec == "fp64" else 1e-5
+    tol = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-5}[prec]
     ref, st = O.mpa_propagate(w.A0, m, L, w.dz, w.M, tol=tol, max_iter=40, return_stats=True)
     plan = make_plan(w, prec, tol=tol, max_iter=40)
     res = plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, w.M)
     err = relmax(res.field.cpu().numpy(), ref)
     print(f"[{prec} cfg{cfg}] error {err:.3e} iters gpu {res.stats['iterations']} oracle {sum(st.iterations)}",
           flush=True)
-    assert err < (1e-8 if prec == "fp64" else 2e-5)
+    assert err < {"fp64": 1e-8, "fp32": 2e-5, "bf16x3": 1e-3}[prec]
