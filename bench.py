@@ -39,17 +39,25 @@ TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}
 
 
-def work_per_eval(kind: str, N: int, Nt: int, prec: str) -> dict:
-    """Algorithmic work of one kernel kind for one sub-step integrand."""
+def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0) -> dict:
+    """Algorithmic work of one kernel kind for one sub-step integrand.
+
+    rank > 0: the plan contracts through the factor S^ = U V (U: Np x r), so the
+    Raman convolution acts on r rows and the products are 2 r Np Nt each.
+    bf16x3 executes three bf16 products per useful multiply-add; the useful
+    count is what is reported (against the matching useful-work peak)."""
     Np = N * (N + 1) // 2
     rs = 8 if prec == "fp64" else 4
     cs = 2 * rs
     fft = 5.0 * Nt * math.log2(Nt)
+    rows = rank if rank else Np           # rows that are convolved
     if kind == "contract":
-        # bf16x3 executes three bf16 products per useful multiply-add; the useful (packed) count is reported
-        return {"bound": "mfma", "flops": 2.0 * Np * Np * Nt, "bytes": Np * Nt * rs + 2 * N * Nt * cs}
+        k = rank if rank else Np
+        return {"bound": "mfma", "flops": 2.0 * Np * k * Nt, "bytes": k * Nt * rs + 2 * N * Nt * cs}
+    if kind == "project":
+        return {"bound": "mfma", "flops": 2.0 * rank * Np * Nt, "bytes": N * Nt * cs + rank * Nt * rs}
     if kind == "pairs_raman":
-        return {"bound": "alu", "flops": math.ceil(Np / 2) * 2 * fft, "bytes": N * Nt * cs + Np * Nt * rs}
+        return {"bound": "alu", "flops": math.ceil(rows / 2) * 2 * fft, "bytes": N * Nt * cs + rows * Nt * rs}
     if kind in ("phase_to_time", "spectral_out"):
         return {"bound": "hbm", "flops": N * fft, "bytes": 2 * N * Nt * cs}
     if kind == "trapz":
@@ -81,6 +89,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     import torch
     from paper_1708_05324_amd import gmmpa
     plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30)
+    rank = plan.rank()
     dtype = torch.complex128 if prec == "fp64" else torch.complex64
     A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
     Ls = w.M * w.dz
@@ -124,6 +133,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
         "stats": st,
         "prof": prof,
         "breakdown": breakdown,
+        "rank": rank,
     }
     if lat:
         lat.sort()
@@ -134,12 +144,12 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     return out
 
 
-def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str):
+def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str, rank: int = 0):
     """Roofline entry of the kernel kind with the largest total time."""
     kind = max(prof, key=lambda k: prof[k][0])
     total_ms, launches = prof[kind]
     evals = stats["evaluations"]          # sub-step integrands = units processed by all counted launches
-    wk = work_per_eval(kind, N, Nt, prec)
+    wk = work_per_eval(kind, N, Nt, prec, rank)
     sec = total_ms * 1e-3
     if wk["bound"] == "mfma":
         achieved = wk["flops"] * evals / sec / 1e12
@@ -195,6 +205,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=20)
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    ap.add_argument("--sweep-M", action="store_true",
+                    help="only run the parallel-extent sweep M = 1..40 (M = 1 is the serial trapezoid) on the "
+                         "10-mode 2^14 workload with z_NL/dz = 200, and print its own JSON line")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -207,6 +222,32 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
+    if args.sweep_M:
+        w = synth.fig3_workload()
+        out = {"sweep": "parallel extent M", "workload": w.name, "n_modes": w.n_modes, "nt": w.nt,
+               "dz_um": round(w.dz * 1e6, 4), "precision": args.precision, "tol": TOL[args.precision], "points": []}
+        for M in (1, 2, 5, 10, 20, 40):
+            w.M = M
+            n_large = max(4, 200 // M)            # about the same fibre length for every M
+            r = run_gpu(args.precision, w, n_large, 2, 0, False)
+            out["points"].append({"M": M, "small_steps_per_s": round(r["small_steps_per_s"], 1),
+                                  "iterations_per_large_step": round(r["iterations_per_large_step"], 3),
+                                  "evaluations_per_s": round(r["evaluations_per_s"], 1)})
+            print(f"M={M}: {out['points'][-1]}", file=sys.stderr, flush=True)
+        base = out["points"][0]["small_steps_per_s"]
+        for pt in out["points"]:
+            pt["speedup_vs_serial"] = round(pt["small_steps_per_s"] / base, 3)
+        print(json.dumps(out), flush=True)
+        return
+    if args.copy_probe:
+        n = 256 * 2 ** 20 // 4
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}), flush=True)
+        return
     gmmpa.load_library()
     w = synth.config3()
     N, Nt = w.n_modes, w.nt
@@ -237,7 +278,7 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "n_modes": N, "nt": Nt, "window_ps": round(Nt * w.dt * 1e12, 3),
-                   "M": w.M, "dz_um": round(w.dz * 1e6, 4), "tol": TOL[args.precision], "fR": w.fR,
+                   "M": w.M, "coupling_rank": main_run["rank"], "dz_um": round(w.dz * 1e6, 4), "tol": TOL[args.precision], "fR": w.fR,
                    "self_steepening": w.self_steepening, "step": "one MPA large step (M small steps)",
                    "parallelism": "single GPU"},
         "iterations_per_large_step": round(main_run["iterations_per_large_step"], 3),
@@ -248,7 +289,8 @@ def main():
         "compare": extra,
     }
     if main_run["prof"]:
-        line["roofline"] = roofline(main_run["prof"], main_run["stats"], N, Nt, args.precision, workload)
+        line["roofline"] = roofline(main_run["prof"], main_run["stats"], N, Nt, args.precision, workload,
+                                    main_run["rank"])
     if main_run["breakdown"]:
         line["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in main_run["breakdown"].items()}
     if not args.no_cpu_baseline:

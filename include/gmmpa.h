@@ -65,6 +65,9 @@ typedef struct {
   double tol;           /* threshold on ||psi^(n+1) - psi^(n)|| / ||psi^(n+1)|| (FP64) */
   int max_iter;         /* iteration cap per large step (>= 1) */
   int fixed_iters;      /* > 0: run exactly this many iterations per large step, ignore tol */
+  int factor_policy;    /* 0: when the Raman term is on and the packed coupling matrix S^ has numerical
+                           rank r <= min(64, Np/2), contract through its factor S^ = U V so only r rows
+                           are convolved (same result to rounding); 1: always use S^ itself */
 } gmm_params;
 
 typedef struct {
@@ -139,6 +142,10 @@ const char* gmm_last_error(void);
 /* Device bytes currently held by the plan (constants + workspace). */
 long long gmm_plan_device_bytes(gmm_plan plan);
 
+/* Rank r of the factor S^ = U V the plan contracts through (factor_policy 0,
+ * Raman on, r small enough), or 0 when it uses the packed matrix itself. */
+int gmm_plan_rank(gmm_plan plan);
+
 /*
  * Per-kernel timing with HIP events on the plan's stream (for benchmarks).
  * gmm_profile_enable(plan, kinds) clears the totals and brackets every later
@@ -150,13 +157,14 @@ long long gmm_plan_device_bytes(gmm_plan plan);
  * summed duration in ms and the number of counted launches.
  */
 #define GMM_PROF_PHASE 0    /* phase factors + inverse transform (sub-step fields) */
-#define GMM_PROF_PAIRS 1    /* pair products + Raman convolution */
+#define GMM_PROF_PAIRS 1    /* pair products + Raman convolution (rank-r route: convolution of Y) */
 #define GMM_PROF_CONTRACT 2 /* coupling contraction (MFMA) + mode projection */
 #define GMM_PROF_SPECTRAL 3 /* forward transform + shock + back-phase */
 #define GMM_PROF_TRAPZ 4    /* cumulative trapezoid + FP64 partial norms */
 #define GMM_PROF_NORM 5     /* norm reduction + stop decision */
 #define GMM_PROF_CLOSE 6    /* large-step close */
-#define GMM_PROF_KINDS 7
+#define GMM_PROF_PROJECT 7  /* rank-r route: Y = V B on MFMA (pair products formed on the fly) */
+#define GMM_PROF_KINDS 8
 #define GMM_PROF_ALL ((1 << GMM_PROF_KINDS) - 1)
 int gmm_profile_enable(gmm_plan plan, int kinds);
 int gmm_profile_read(gmm_plan plan, double* total_ms, long long* launches, int n_kinds);

@@ -21,13 +21,13 @@
 
 namespace gmm {
 
-template <int LOGN_, int ELEM_BYTES>
+template <int LOGN_, int ELEM_BYTES, int MAX_LOGR = 5>
 struct FftShape {
   static constexpr int LOGN = LOGN_;
   static constexpr int N = 1 << LOGN;
   // 32 points per thread for FP32 rows of 2^10 and more; 16 for FP64 rows
   // (32 complex doubles would need 128 VGPRs for the data alone).
-  static constexpr int LOGR = (ELEM_BYTES == 4 && LOGN >= 10) ? 5 : 4;
+  static constexpr int LOGR = (ELEM_BYTES == 4 && LOGN >= 10 && MAX_LOGR >= 5) ? 5 : 4;
   static constexpr int R = 1 << LOGR;
   static constexpr int THREADS = N / R;
   static constexpr int NFULL = LOGN / LOGR;
@@ -43,7 +43,6 @@ struct FftShape {
   static_assert(LOGN >= 8 && LOGN <= 15, "row length must be 2^8 .. 2^15");
 };
 
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
 // cos/sin of 2*pi*m/32, m = 0..31, from the first-octant table by symmetry.
 __device__ __forceinline__ constexpr double c32_table(int r) {
@@ -106,25 +105,39 @@ __device__ __forceinline__ void dft_reg(cplx<T>* u) {
   }
 }
 
+// Twiddle bases of pass I for this thread: wp[b][e] = W^(2^e k_b), with
+// W = exp(SIGN 2 pi i / (Ns P)) and k_b = (tid + b THREADS) mod Ns; the pass
+// multiplies them along the set bits of q to form W^(q k_b).  Loaded one pass
+// ahead so their latency overlaps the LDS exchange.
+template <class S, int I, typename T, int SIGN>
+struct PassTwiddles {
+  static constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
+  static constexpr int LNS = S::log_stride(I), NS = 1 << LNS;
+  static constexpr bool USED = NS > 1;
+  cplx<T> wp[USED ? B : 1][USED ? LP : 1];
+  __device__ __forceinline__ void load(int tid, const cplx<T>* __restrict__ tw) {
+    if constexpr (USED) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int k = (tid + b * S::THREADS) & (NS - 1);
+#pragma unroll
+        for (int e = 0; e < LP; ++e) {
+          wp[b][e] = tw[(k << e) << (S::LOGN - LNS - LP)];  // table holds exp(-2 pi i m / N)
+          if (SIGN > 0) wp[b][e].im = -wp[b][e].im;
+        }
+      }
+    }
+  }
+};
+
 // One Stockham pass: butterflies read at j + q*N/P, write at
 // (j / Ns) * Ns * P + j % Ns + q * Ns, with twiddles exp(SIGN 2 pi i q (j % Ns) / (Ns P)).
 template <class S, int I, typename T, int SIGN>
-__device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], int tid, const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], const PassTwiddles<S, I, T, SIGN>& tws) {
   constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
-  constexpr int LNS = S::log_stride(I), NS = 1 << LNS;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const int j = tid + b * S::THREADS;
-    if constexpr (NS > 1) {
-      // W^(q k), W = exp(SIGN 2 pi i / (Ns P)): table entries W^(2^e k), e < LP,
-      // multiplied along the set bits of q (at most LP - 1 products).
-      const int k = j & (NS - 1);
-      cplx<T> wp[LP];
-#pragma unroll
-      for (int e = 0; e < LP; ++e) {
-        wp[e] = tw[(k << e) << (S::LOGN - LNS - LP)];  // table holds exp(-2 pi i m / N)
-        if (SIGN > 0) wp[e].im = -wp[e].im;
-      }
+    if constexpr (PassTwiddles<S, I, T, SIGN>::USED) {
 #pragma unroll
       for (int q = 1; q < P; ++q) {
         cplx<T> w = {T(1), T(0)};
@@ -132,7 +145,7 @@ __device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], int tid, co
 #pragma unroll
         for (int e = 0; e < LP; ++e)
           if (q & (1 << e)) {
-            w = first ? wp[e] : cmul(w, wp[e]);
+            w = first ? tws.wp[b][e] : cmul(w, tws.wp[b][e]);
             first = false;
           }
         v[b * P + q] = cmul(v[b * P + q], w);
@@ -140,6 +153,16 @@ __device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], int tid, co
     }
     dft_reg<T, P, SIGN>(&v[b * P]);
   }
+}
+
+// LDS padding of the exchange after pass I: one slot every 2^s elements with
+// s = max(log2 P_I, 4), so the stride-P (or run-of-Ns) writes of the pass fall
+// on distinct banks; never more than S::N / 16 extra slots.
+template <class S, int I>
+__device__ __forceinline__ int lds_pad_x(int i) {
+  constexpr int LP = S::logp(I);
+  constexpr int SH = LP > 4 ? LP : 4;
+  return i + (i >> SH);
 }
 
 // Write pass I's outputs to LDS (one component), read pass I+1's inputs.
@@ -154,7 +177,8 @@ __device__ __forceinline__ void fft_exchange_component(cplx<T> (&v)[S::R], T* ld
     const int j = tid + b * S::THREADS;
     const int base = ((j >> LNS) << (LNS + LP)) + (j & (NS - 1));
 #pragma unroll
-    for (int q = 0; q < P; ++q) lds[lds_pad(base + (q << LNS))] = IMAG ? v[b * P + q].im : v[b * P + q].re;
+    for (int q = 0; q < P; ++q)
+      lds[lds_pad_x<S, I>(base + (q << LNS))] = IMAG ? v[b * P + q].im : v[b * P + q].re;
   }
   __syncthreads();
 #pragma unroll
@@ -162,19 +186,22 @@ __device__ __forceinline__ void fft_exchange_component(cplx<T> (&v)[S::R], T* ld
     const int j = tid + b * S::THREADS;
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
-      T x = lds[lds_pad(j + q * (S::N / P2))];
+      T x = lds[lds_pad_x<S, I>(j + q * (S::N / P2))];
       if (IMAG) v[b * P2 + q].im = x; else v[b * P2 + q].re = x;
     }
   }
 }
 
 template <class S, int I, typename T, int SIGN>
-__device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw) {
-  fft_pass_compute<S, I, T, SIGN>(v, tid, tw);
+__device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw,
+                                           const PassTwiddles<S, I, T, SIGN>& tws) {
+  fft_pass_compute<S, I, T, SIGN>(v, tws);
   if constexpr (I + 1 < S::NPASS) {
+    PassTwiddles<S, I + 1, T, SIGN> next;
+    next.load(tid, tw);
     fft_exchange_component<S, I, T, false>(v, lds, tid);
     fft_exchange_component<S, I, T, true>(v, lds, tid);
-    fft_passes<S, I + 1, T, SIGN>(v, lds, tid, tw);
+    fft_passes<S, I + 1, T, SIGN>(v, lds, tid, tw, next);
   }
 }
 
@@ -182,7 +209,8 @@ __device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, 
 // `lds` must hold S::LDS_ELEMS scalars of type T.  All threads must call it.
 template <class S, typename T, int SIGN>
 __device__ __forceinline__ void block_fft(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw) {
-  fft_passes<S, 0, T, SIGN>(v, lds, tid, tw);
+  PassTwiddles<S, 0, T, SIGN> first;  // pass 0 has Ns = 1: no twiddles
+  fft_passes<S, 0, T, SIGN>(v, lds, tid, tw, first);
 }
 
 }  // namespace gmm

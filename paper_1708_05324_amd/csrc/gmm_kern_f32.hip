@@ -23,39 +23,51 @@ hipError_t launch_pairs_bf16(int logn, bool raman, const cplx<float>* A, uint32_
   return hipGetLastError();
 }
 
-template <int RT>
+template <int RT, int KPAD>
 static int contract_bf16_blocks() {
   static int blocks = 0;
   if (blocks == 0) {
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_bf16<RT>, 256,
-                                                     ContractBf16Shape<RT>::lds_bytes()) != hipSuccess ||
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_bf16<RT, KPAD>, 256,
+                                                     ContractBf16Shape<RT, KPAD>::lds_bytes()) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-      cus = 256;
-    blocks = per_cu * cus;
+    blocks = per_cu * device_cus();
   }
   return blocks;
 }
 
-hipError_t launch_contract_bf16(int rt, const void* Shi, const void* Slo, const uint32_t* Bhi, const uint32_t* Blo,
-                                cplx<float>* A_NL, const int* pidx, int N, int Nt, int count, const Ctrl* ctrl,
-                                hipStream_t s) {
+hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* Slo, const uint32_t* Bhi,
+                                const uint32_t* Blo, cplx<float>* A_NL, const int* pidx, int N, int Nt, int count,
+                                const Ctrl* ctrl, hipStream_t s) {
   const int ntiles = count * (Nt / 64);
-#define GMM_BF_CASE(R)                                                                                            \
-  if (rt == R) {                                                                                                  \
-    const int nb = std::min(ntiles, contract_bf16_blocks<R>());                                                   \
-    hipLaunchKernelGGL((k_contract_bf16<R>), dim3(nb), dim3(256), ContractBf16Shape<R>::lds_bytes(), s,          \
+#define GMM_BF_CASE(R, KP)                                                                                        \
+  if (rt == R && kpad == KP) {                                                                                    \
+    const int nb = std::min(ntiles, contract_bf16_blocks<R, KP>());                                               \
+    hipLaunchKernelGGL((k_contract_bf16<R, KP>), dim3(nb), dim3(256), (ContractBf16Shape<R, KP>::lds_bytes()), s, \
                        (const uint4*)Shi, (const uint4*)Slo, (const uint4*)Bhi, (const uint4*)Blo, A_NL, pidx, N, \
                        Nt, ntiles, ctrl);                                                                         \
     return hipGetLastError();                                                                                     \
   }
-  GMM_BF_CASE(1)
-  GMM_BF_CASE(2)
+  GMM_BF_CASE(1, 128)
+  GMM_BF_CASE(2, 128)
+  GMM_BF_CASE(1, 64)
+  GMM_BF_CASE(2, 64)
 #undef GMM_BF_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
+                            const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
+  using T = float;
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, 4>;
+    const int total = (R + 1) / 2 * count;
+    dim3 grid(8 * ((total + 7) / 8));
+    hipLaunchKernelGGL((k_conv<float, LOGN, true>), grid, dim3(S::THREADS), 0, s, Y, nullptr, Bhi, Blo, R, RQ,
+                       count, 8, Gs, tw, ctrl);
+  });
+  return hipGetLastError();
 }
 
 }  // namespace gmm

@@ -370,25 +370,32 @@ __device__ __forceinline__ void project_modes(const T* sC, const cplx<T>* sA, co
   }
 }
 
-// Contraction for Rpad <= 128 (N <= 15), persistent over 64-column tiles.
-// Each wave keeps its 16 RT rows of S^ (all K) in registers for the life of
+// Contraction for Rpad <= 128 (N <= 15), persistent over 64-column tiles:
+// C = S^ B' (packed matrix, K = Np) or C = U Y' (rank-r factor, K = r).
+// Each wave keeps its 16 RT rows of the matrix (all K) in registers for the life of
 // the block, so the coupling matrix is read once per block; B' fragments are
 // loaded straight from global memory (the four waves of a block read the same
 // tile, which stays in L1/L2).  Rows k >= Np of S^ are zero, so B' row indices
 // are clamped to Np - 1 instead of branching.
 // LDS: C tile [RPAD][64], A tile [N][64] complex, pair-index table [N][N].
 template <int RT, typename T>
-constexpr size_t contract_reg_lds() {
+constexpr size_t contract_reg_lds_impl() {
   return (size_t)64 * RT * 64 * sizeof(T) + (size_t)ContractShape<RT>::NMAX * 64 * sizeof(cplx<T>) +
          (size_t)ContractShape<RT>::NMAX * ContractShape<RT>::NMAX * sizeof(int);
 }
 
-template <typename T, int RT>
+template <int RT, typename T>
+constexpr size_t contract_reg_lds() { return contract_reg_lds_impl<RT, T>(); }
+
+// KPAD: padded K (64 RT for the packed matrix; 64 for a rank-r factor U).
+// Kv valid B' rows per sub-step, laid out [count][Kv][Nt].
+template <typename T, int RT, int KPAD>
 __global__ __launch_bounds__(256) void k_contract_reg(
     const T* __restrict__ ST, const T* __restrict__ Bp, cplx<T>* A_NL, const int* __restrict__ pidx, int N,
-    int Np, int Nt, int ntiles, const Ctrl* ctrl) {
+    int Kv, int Nt, int ntiles, const Ctrl* ctrl) {
   using CS = ContractShape<RT>;
-  constexpr int RPAD = CS::RPAD, TN = CS::TN, KS = RPAD / 4;
+  constexpr int RPAD = CS::RPAD, TN = CS::TN, KS = KPAD / 4;
+  const int Np = Kv;
   typedef typename Mfma<T>::acc_t acc_t;
   if (skip_iteration(ctrl)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -451,10 +458,10 @@ __global__ __launch_bounds__(256) void k_contract_reg(
 // The coupling slices (hi, lo) stay in registers; each 64-column tile of B'
 // (both planes, Kpad x 64 x 2 x 2 bytes) is staged in LDS, and the next tile is
 // fetched into registers while the current one is multiplied.
-template <int RT>
+template <int RT, int KPAD_ = 128>
 struct ContractBf16Shape {
   static constexpr int RPAD = 64 * RT;
-  static constexpr int KPAD = 128;  // K up to 128 pairs (N <= 15)
+  static constexpr int KPAD = KPAD_;  // K up to 128 (packed pairs) or 64 (rank-r factor)
   static constexpr int KS = KPAD / 32;
   static constexpr int KB = KPAD / 8;
   static constexpr int TN = 64;
@@ -468,12 +475,12 @@ struct ContractBf16Shape {
   }
 };
 
-template <int RT>
+template <int RT, int KPAD>
 __global__ __launch_bounds__(256) void k_contract_bf16(
     const uint4* __restrict__ Shi, const uint4* __restrict__ Slo, const uint4* __restrict__ Bhi,
     const uint4* __restrict__ Blo, cplx<float>* A_NL, const int* __restrict__ pidx, int N, int Nt, int ntiles,
     const Ctrl* ctrl) {
-  using CS = ContractBf16Shape<RT>;
+  using CS = ContractBf16Shape<RT, KPAD>;
   constexpr int RPAD = CS::RPAD, KS = CS::KS, KB = CS::KB, TN = CS::TN;
   constexpr size_t BC_BYTES = CS::TILE_WORDS4 * 16 > RPAD * TN * 4 ? CS::TILE_WORDS4 * 16 : RPAD * TN * 4;
   if (skip_iteration(ctrl)) return;
@@ -555,6 +562,116 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
 }
 
 // ---------------------------------------------------------------------------
+// Rank-r route for the Raman term.  The packed matrix factors as S^ = U V
+// (U: Np x r, V: r x Np, from the eigen-decomposition of the symmetric pair
+// matrix; r = its numerical rank).  The blended Raman filter g acts on time and
+// S^ on the pair index, so S^ (g * B) = U (g * (V B)): only the r rows of
+// Y = V B need the convolution.
+//
+// k_project: Y_rho(t) = sum_Q V_rho,Q B_Q(t), B_Q = Re(A_m A_n^*) formed from
+// the field tile in LDS.  One block = one 64-column tile of one sub-step,
+// persistent; wave w owns columns 16 w .. 16 w + 15 and all RQ (<= 64) rows.
+// V^T [KP][RQ] is staged in LDS once per block; Y is written [count][RQ][Nt].
+template <typename T, int RQ, int KP>
+constexpr size_t project_lds() {
+  return (size_t)KP * RQ * sizeof(T) + (size_t)22 * 64 * sizeof(cplx<T>) + (size_t)KP * sizeof(int2);
+}
+
+template <typename T, int RQ, int KP>
+__global__ __launch_bounds__(256) void k_project(
+    const T* __restrict__ VT, const cplx<T>* __restrict__ A, T* __restrict__ Y, const int2* __restrict__ pairs,
+    int N, int Np, int Nt, int ntiles, const Ctrl* ctrl) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int RTQ = RQ / 16;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sV = reinterpret_cast<T*>(smem_raw);                        // [KP][RQ]
+  cplx<T>* sA = reinterpret_cast<cplx<T>*>(sV + KP * RQ);        // [N][64], N <= 22
+  int2* sQ = reinterpret_cast<int2*>(sA + 22 * 64);              // [KP] pair (m, n); clamped beyond Np
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int i = tid; i < KP * RQ; i += 256) sV[i] = VT[i];
+  for (int i = tid; i < KP; i += 256) sQ[i] = pairs[i < Np ? i : Np - 1];
+  const int tiles_per_j = Nt / 64;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * 64;
+    const cplx<T>* Aj = A + (size_t)jj * N * Nt;
+    __syncthreads();  // sV/sQ staged; previous tile done with sA
+    for (int i = tid; i < N * 64; i += 256) sA[i] = Aj[(size_t)(i >> 6) * Nt + t0 + (i & 63)];
+    __syncthreads();
+    acc_t acc[RTQ];
+#pragma unroll
+    for (int r = 0; r < RTQ; ++r) acc[r] = acc_t{0, 0, 0, 0};
+    const int col = wave * 16 + lr;
+#pragma unroll 4
+    for (int s = 0; s < KP / 4; ++s) {
+      const int k = 4 * s + lk;
+      const int2 mn = sQ[k];
+      const cplx<T> x = sA[mn.x * 64 + col], y = sA[mn.y * 64 + col];
+      const T b = x.re * y.re + x.im * y.im;
+#pragma unroll
+      for (int r = 0; r < RTQ; ++r) acc[r] = Mfma<T>::mma(sV[k * RQ + r * 16 + lr], b, acc[r]);
+    }
+    T* Yj = Y + (size_t)jj * RQ * Nt + t0 + col;
+#pragma unroll
+    for (int r = 0; r < RTQ; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Yj[(size_t)(r * 16 + Mfma<T>::out_row(lk, i)) * Nt] = acc[r][i];
+  }
+}
+
+// k_conv: Y'_rho = g * Y_rho for rows rho < R (pairs of rows as one complex
+// transform, as in k_pairs).  Output [count][R][Nt] in T, or (BF16 split)
+// hi/lo planes [count][KB][Nt][8].  1-D grid in XCD-local order.
+template <typename T, int LOGN, bool BF16OUT>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_conv(
+    const T* __restrict__ Y, T* __restrict__ Yout, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo, int R,
+    int RQ, int count, int KB, const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T)>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int PB = (R + 1) / 2;
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x, jj = w / PB;
+  const int r1 = 2 * (w - jj * PB);
+  const T* y1 = Y + ((size_t)jj * RQ + r1) * S::N;
+  const T* y2 = y1 + S::N;  // row r1 + 1 < RQ (rows up to RQ are allocated; beyond r they are zero)
+  cplx<T> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    z[i] = {y1[t], y2[t]};
+  }
+  block_fft<S, T, +1>(z, lds, tid, tw);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gs[tid + i * S::THREADS]);
+  block_fft<S, T, -1>(z, lds, tid, tw);
+  if constexpr (BF16OUT) {
+    const size_t base = (((size_t)jj * KB + (r1 >> 3)) * S::N) * 4 + ((r1 & 7) >> 1);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) {
+      const int t = tid + i * S::THREADS;
+      const uint32_t h1 = bf16_bits((float)z[i].re), h2 = bf16_bits((float)z[i].im);
+      const uint32_t l1 = bf16_bits((float)z[i].re - bf16_value(h1));
+      const uint32_t l2 = bf16_bits((float)z[i].im - bf16_value(h2));
+      Bhi[base + (size_t)t * 4] = h1 | (h2 << 16);
+      Blo[base + (size_t)t * 4] = l1 | (l2 << 16);
+    }
+  } else {
+    T* o1 = Yout + ((size_t)jj * RQ + r1) * S::N;
+    T* o2 = o1 + S::N;
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) {
+      const int t = tid + i * S::THREADS;
+      o1[t] = z[i].re;
+      o2[t] = z[i].im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a6: I_j(w) = exp(-D_w z_j) * i gamma^ (1 + s w/w0) * F{NL_j}(w),
 // F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt.  grid (N, count); in may alias out.
 template <typename T, int LOGN>
@@ -586,18 +703,23 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_s
 // ---------------------------------------------------------------------------
 // a7 + a8: cumulative trapezoid and the relative change of psi (FP64 sums).
 //   psi_j^(n+1) = psi_0 + dz [ I_0/2 + sum_{k<j} I_k + I_j/2 ],  j = 1..M
-// first != 0: the previous iterate is psi_0 for every j (the initial guess).
+// first != 0: the previous iterate is psi_0 for every j (the initial guess),
+// and I_0 arrives in I0 as part of the first iteration's batch; it is copied to
+// I0_keep for the later iterations of the large step.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trapz(
     const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
-    cplx<T>* __restrict__ psi, int first, int M, long nn, T dz, double* __restrict__ partials, const Ctrl* ctrl) {
+    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, int first, int M, long nn, T dz,
+    double* __restrict__ partials, const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
   __shared__ double red[2][256];
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
   if (e < nn) {
     const cplx<T> p0 = psi0[e];
-    const cplx<T> h0 = cscale(I0[e], T(0.5));
+    const cplx<T> i0 = I0[e];
+    if (first) I0_keep[e] = i0;
+    const cplx<T> h0 = cscale(i0, T(0.5));
     cplx<T> run = {0, 0};
     for (int j = 0; j < M; ++j) {
       const cplx<T> ij = I[(size_t)j * nn + e];

@@ -19,13 +19,18 @@ struct Launch {
                                   const Ctrl* ctrl, hipStream_t s);
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
                           int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
-  static hipError_t contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
-                             int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+  // kpad = 0: packed matrix with K = Rpad (kv = Np rows per sub-step); kpad = 64: rank factor U (kv = RQ).
+  static hipError_t contract(int rt, int kpad, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N,
+                             int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t project(int rq, int kp, const T* VT, const cplx<T>* A, T* Y, const int2* pairs, int N, int Np,
+                            int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t conv(int logn, const T* Y, T* Yout, int R, int RQ, int count, const cplx<T>* Gs,
+                         const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
                                  int count, int j0, double dz, double domega, double gscale, double inv_omega0,
                                  int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
-  static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, int first, int M,
-                          long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
+                          int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
   static hipError_t close(const cplx<T>* src, cplx<T>* dst, const double* coef, int nb, int nt, long nn, double z,
                           double domega, hipStream_t s);
   static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
@@ -38,9 +43,11 @@ constexpr int kBf16Kpad = 128;
 hipError_t launch_pairs_bf16(int logn, bool raman, const cplx<float>* A, uint32_t* Bhi, uint32_t* Blo,
                              const int2* pairs, int N, int Np, int count, const cplx<float>* Gs,
                              const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
-hipError_t launch_contract_bf16(int rt, const void* Shi, const void* Slo, const uint32_t* Bhi, const uint32_t* Blo,
-                                cplx<float>* A_NL, const int* pidx, int N, int Nt, int count, const Ctrl* ctrl,
-                                hipStream_t s);
+hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* Slo, const uint32_t* Bhi,
+                                const uint32_t* Blo, cplx<float>* A_NL, const int* pidx, int N, int Nt, int count,
+                                const Ctrl* ctrl, hipStream_t s);
+hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
+                            const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);

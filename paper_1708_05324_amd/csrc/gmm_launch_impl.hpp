@@ -77,14 +77,13 @@ hipError_t Launch<T>::pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const
   return hipGetLastError();
 }
 
-template <typename T, int RT>
+template <typename T, int RT, int KPAD>
 int contract_reg_blocks() {
   static int blocks = 0;
   if (blocks == 0) {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_reg<T, RT>, 256,
-                                                     contract_reg_lds<RT, T>()) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_reg<T, RT, KPAD>, 256,
+                                                     contract_reg_lds<RT, T>()) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -95,22 +94,33 @@ int contract_reg_blocks() {
   return blocks;
 }
 
+inline int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+  }
+  return cus;
+}
+
 template <typename T>
-hipError_t Launch<T>::contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N, int Np,
-                               int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+hipError_t Launch<T>::contract(int rt, int kpad, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N,
+                               int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
   const int ntiles = count * (Nt / 64);
-  if (rt <= 2) {  // coupling slice resident in registers, persistent blocks
-#define GMM_RT_REG(R)                                                                                        \
-  if (rt == R) {                                                                                             \
-    const int nb = std::min(ntiles, contract_reg_blocks<T, R>());                                            \
-    hipLaunchKernelGGL((k_contract_reg<T, R>), dim3(nb), dim3(256), (contract_reg_lds<R, T>()), s, ST, Bp, A_NL, \
-                       pidx, N, Np, Nt, ntiles, ctrl);                                                       \
+#define GMM_RT_REG(R, KP)                                                                                   \
+  if (rt == R && (kpad == KP || (kpad == 0 && KP == 64 * R))) {                                              \
+    const int nb = std::min(ntiles, contract_reg_blocks<T, R, KP>());                                        \
+    hipLaunchKernelGGL((k_contract_reg<T, R, KP>), dim3(nb), dim3(256), (contract_reg_lds<R, T>()), s, ST, Bp, \
+                       A_NL, pidx, N, kv, Nt, ntiles, ctrl);                                                 \
     return hipGetLastError();                                                                                \
   }
-    GMM_RT_REG(1)
-    GMM_RT_REG(2)
+  GMM_RT_REG(1, 64)
+  GMM_RT_REG(2, 128)
+  GMM_RT_REG(2, 64)
 #undef GMM_RT_REG
-  }
+  if (kpad != 0) return hipErrorInvalidValue;
   dim3 grid(ntiles);
   switch (rt) {
 #define GMM_RT_CASE(R)                                                                                         \
@@ -121,16 +131,48 @@ hipError_t Launch<T>::contract(int rt, const T* ST, const T* Bp, cplx<T>* A_NL, 
                                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (attr != hipSuccess) return attr;                                                                     \
     }                                                                                                          \
-    hipLaunchKernelGGL((k_contract<T, R>), grid, dim3(256), lds, s, ST, Bp, A_NL, pidx, N, Np, Nt, ctrl);      \
+    hipLaunchKernelGGL((k_contract<T, R>), grid, dim3(256), lds, s, ST, Bp, A_NL, pidx, N, kv, Nt, ctrl);      \
   } break;
-    GMM_RT_CASE(1)
-    GMM_RT_CASE(2)
     GMM_RT_CASE(3)
     GMM_RT_CASE(4)
 #undef GMM_RT_CASE
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::project(int rq, int kp, const T* VT, const cplx<T>* A, T* Y, const int2* pairs, int N, int Np,
+                              int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+  const int ntiles = count * (Nt / 64);
+  const int nb = std::min(ntiles, 2 * device_cus());
+#define GMM_PROJ(RQ, KP)                                                                                     \
+  if (rq == RQ && kp == KP) {                                                                                 \
+    hipLaunchKernelGGL((k_project<T, RQ, KP>), dim3(nb), dim3(256), (project_lds<T, RQ, KP>()), s, VT, A, Y,  \
+                       pairs, N, Np, Nt, ntiles, ctrl);                                                       \
+    return hipGetLastError();                                                                                 \
+  }
+#define GMM_PROJ_K(RQ) GMM_PROJ(RQ, 64) GMM_PROJ(RQ, 128) GMM_PROJ(RQ, 192) GMM_PROJ(RQ, 256)
+  GMM_PROJ_K(16)
+  GMM_PROJ_K(32)
+  GMM_PROJ_K(48)
+  GMM_PROJ_K(64)
+#undef GMM_PROJ_K
+#undef GMM_PROJ
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t Launch<T>::conv(int logn, const T* Y, T* Yout, int R, int RQ, int count, const cplx<T>* Gs,
+                           const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, (int)sizeof(T)>;
+    const int total = (R + 1) / 2 * count;
+    dim3 grid(8 * ((total + 7) / 8));
+    hipLaunchKernelGGL((k_conv<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, Y, Yout, nullptr, nullptr, R, RQ,
+                       count, 0, Gs, tw, ctrl);
+  });
   return hipGetLastError();
 }
 
@@ -147,10 +189,11 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
 }
 
 template <typename T>
-hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, int first,
-                            int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, first, M, nn, dz,
-                     partials, ctrl);
+hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi,
+                            cplx<T>* I0_keep, int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, first, M, nn,
+                     dz, partials, ctrl);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -146,6 +147,14 @@ struct gmm_plan_s {
   void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed (FP64 / FP32)
   void* Shi = nullptr;     // [rpad][128] bf16 high part of the packed matrix, K contiguous (BF16X3)
   void* Slo = nullptr;     // [rpad][128] bf16 low part
+  // rank-r route (Raman on, low-rank packed matrix): S^ = U V
+  bool factored = false;
+  int rank = 0, rq = 0, kp = 0;  // r, r rounded up to 16, Np rounded up to 64
+  void* VT = nullptr;      // [kp][rq] V transposed, field precision
+  void* UT = nullptr;      // [64][rpad] U transposed (contraction operand, K = 64)
+  void* Uhi = nullptr;     // [rpad][64] bf16 split of U, K contiguous (BF16X3)
+  void* Ulo = nullptr;
+  void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
   // workspace
@@ -174,7 +183,7 @@ int dev_alloc(long long* counter, T** ptr, size_t bytes) {
 }
 
 void free_workspace(gmm_plan_s* P) {
-  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp}) {
+  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp, &P->Y}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
@@ -202,11 +211,14 @@ int ensure_workspace(gmm_plan_s* P, int cap) {
   if ((rc = dev_alloc(c, &P->psi0, fb)) || (rc = dev_alloc(c, &P->I0, fb)) || (rc = dev_alloc(c, &P->psi, fb * cap)) ||
       (rc = dev_alloc(c, &P->work, fb * cap)) ||
       (rc = dev_alloc(c, &P->Bp, bp_bytes(P, cap))) ||
-      (rc = dev_alloc(c, &P->partials, 2 * sizeof(double) * gmm::trapz_blocks((long)P->N * P->nt)))) {
+      (rc = dev_alloc(c, &P->partials, 2 * sizeof(double) * gmm::trapz_blocks((long)P->N * P->nt))) ||
+      (P->factored && (rc = dev_alloc(c, &P->Y, (size_t)cap * P->rq * P->nt * P->esz)))) {
     free_workspace(P);
     return rc;
   }
-  if (P->bf16) {  // pair slots beyond Np are read by the contraction and must stay zero
+  // BF16 pair slots beyond Np, and rows R..RQ-1 of the rank-r route, are read
+  // by the contraction (with zero coefficients) but never written: keep them 0.
+  if (P->bf16 || P->factored) {
     if (hipMemset(P->Bp, 0, bp_bytes(P, cap)) != hipSuccess) {
       free_workspace(P);
       return fail(GMM_ERR_HIP, "hipMemset of the pair buffer failed");
@@ -233,21 +245,42 @@ struct Runner {
     cplx<T>* W = (cplx<T>*)P->work;
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                      tw(), ctrl, P->stream));
-    if constexpr (std::is_same<T, float>::value) {
+    if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
+      T* Y = (T*)P->Y;
+      GMM_LAUNCH(P, GMM_PROF_PROJECT, Launch<T>::project(P->rq, P->kp, (const T*)P->VT, W, Y, P->pairs, P->N, P->Np,
+                                                       P->nt, count, ctrl, P->stream));
+      const int R = P->rank + (P->rank & 1);
+      if constexpr (std::is_same<T, float>::value) {
+        if (P->bf16) {
+          uint32_t* bhi = (uint32_t*)P->Bp;
+          uint32_t* blo = bhi + bp_plane_words(P);
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
+                                                              (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, 64, P->Uhi, P->Ulo, bhi, blo, W,
+                                                                     P->pidx, P->N, P->nt, count, ctrl, P->stream));
+        }
+      }
+      if (!P->bf16) {
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
+                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)P->Bp, W, P->pidx,
+                                                             P->N, P->rq, P->nt, count, ctrl, P->stream));
+      }
+    } else if constexpr (std::is_same<T, float>::value) {
       if (P->bf16) {
         uint32_t* bhi = (uint32_t*)P->Bp;
         uint32_t* blo = bhi + bp_plane_words(P);
         GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
                                                              count, (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
-        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, P->Shi, P->Slo, bhi, blo, W, P->pidx, P->N,
-                                                                   P->nt, count, ctrl, P->stream));
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, 128, P->Shi, P->Slo, bhi, blo, W, P->pidx,
+                                                                   P->N, P->nt, count, ctrl, P->stream));
       }
     }
-    if (!P->bf16) {
+    if (!P->bf16 && !P->factored) {
       GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
-      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, (const T*)P->ST, (const T*)P->Bp, W, P->pidx, P->N,
-                                                           P->Np, P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
+                                                           P->N, P->Np, P->nt, count, ctrl, P->stream));
     }
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
                                     P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), ctrl,
@@ -255,13 +288,20 @@ struct Runner {
     return GMM_OK;
   }
 
+  // One iteration over the m sub-steps of a large step.  The first iteration
+  // also evaluates I_0 = N~[A(z0)] in the same launches (sub-step 0, no phase),
+  // since every sub-step then reads psi_0; its trapezoid copies I_0 aside.
   int iteration(int m, double dz, bool first) {
     const long nn = (long)P->N * P->nt;
-    const cplx<T>* src = first ? (const cplx<T>*)P->psi0 : (const cplx<T>*)P->psi;
-    int rc = eval(src, first ? 0 : P->N, m, 1, dz, (cplx<T>*)P->work, P->ctrl);
+    cplx<T>* W = (cplx<T>*)P->work;
+    int rc = first ? eval((const cplx<T>*)P->psi0, 0, m + 1, 0, dz, W, P->ctrl)
+                   : eval((const cplx<T>*)P->psi, P->N, m, 1, dz, W, P->ctrl);
     if (rc) return rc;
-    GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, (const cplx<T>*)P->I0, (const cplx<T>*)P->work,
-                             (cplx<T>*)P->psi, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl, P->stream));
+    const cplx<T>* I0 = first ? W : (const cplx<T>*)P->I0;
+    const cplx<T>* I = first ? W + nn : W;
+    GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
+                                                   (cplx<T>*)P->I0, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl,
+                                                   P->stream));
     GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol, P->prm.fixed_iters,
                                    P->prm.max_iter, P->stream));
     return GMM_OK;
@@ -292,7 +332,7 @@ struct Runner {
                                                                             : (long)std::ceil(r);
     if (n_small < 1) n_small = 1;
     const double dz = L / (double)n_small;
-    int rc = ensure_workspace(P, M);
+    int rc = ensure_workspace(P, M + 1);  // the first iteration also evaluates sub-step 0
     if (rc) return rc;
     gmm_stats s{};
     s.dz_used = dz;
@@ -305,8 +345,6 @@ struct Runner {
     while (done < n_small) {
       const int m = (int)std::min<long>(M, n_small - done);
       GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));
-      // I_0 = N~[A(z0)] (no phase: z = 0), unguarded
-      if ((rc = eval((const cplx<T>*)P->psi0, 0, 1, 0, dz, (cplx<T>*)P->I0, nullptr))) return rc;
       int n_enq = 0;
       if (P->prm.fixed_iters > 0) {
         for (; n_enq < P->prm.fixed_iters; ++n_enq) {
@@ -396,6 +434,44 @@ int upload_typed(gmm_plan_s* P, const std::vector<double>& ST, const std::vector
   return GMM_OK;
 }
 
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major,
+// destroyed).  Eigenvalues on return in a[i*n+i]; eigenvectors are the columns of v.
+void jacobi_eigen(int n, std::vector<double>& a, std::vector<double>& v) {
+  v.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+  double total = 0.0;
+  for (double x : a) total += x * x;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a[(size_t)p * n + q] * a[(size_t)p * n + q];
+    if (off <= 1e-32 * total) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[(size_t)p * n + q];
+        if (std::fabs(apq) <= 1e-300) continue;
+        const double theta = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+          a[(size_t)k * n + p] = c * akp - sn * akq;
+          a[(size_t)k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+          a[(size_t)p * n + k] = c * apk - sn * aqk;
+          a[(size_t)q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+          v[(size_t)k * n + p] = c * vkp - sn * vkq;
+          v[(size_t)k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+}
+
 // Host bf16 (round to nearest even) of a float.
 uint16_t host_bf16(float x) {
   uint32_t u;
@@ -429,6 +505,87 @@ int upload_bf16_split(gmm_plan_s* P, const std::vector<double>& ST) {
   return GMM_OK;
 }
 
+// Rank-r factor of the packed matrix: S^ = Sbar W with Sbar_{(pl),(mn)} = S_plmn
+// symmetric and W = diag(w_mn); Sbar = Q L Q^T gives U = Q_r L_r, V = Q_r^T W.
+// Used only when the Raman term is on, r <= min(64, Np/2), rt <= 2, and U V
+// reproduces S^ to 1e-12 of its largest entry.
+template <typename T>
+int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, const std::vector<double>& ST) {
+  const int Np = P->Np, N = P->N;
+  if (!P->raman || P->rt > 2) return GMM_OK;
+  auto S4 = [&](int a, int b, int c, int d) { return SK[(((size_t)a * N + b) * N + c) * N + d]; };
+  std::vector<double> a((size_t)Np * Np), q;
+  double smax = 0;
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) {
+      a[(size_t)i * Np + j] = S4(pairs[i].x, pairs[i].y, pairs[j].x, pairs[j].y);
+      smax = std::max(smax, std::fabs(a[(size_t)i * Np + j]));
+    }
+  for (int i = 0; i < Np; ++i)  // the factor needs the (pl) <-> (mn) symmetry as well
+    for (int j = i + 1; j < Np; ++j)
+      if (std::fabs(a[(size_t)i * Np + j] - a[(size_t)j * Np + i]) > 1e-12 * smax) return GMM_OK;
+  jacobi_eigen(Np, a, q);
+  double lmax = 0;
+  for (int i = 0; i < Np; ++i) lmax = std::max(lmax, std::fabs(a[(size_t)i * Np + i]));
+  std::vector<int> keep;
+  for (int i = 0; i < Np; ++i)
+    if (std::fabs(a[(size_t)i * Np + i]) > 1e-12 * lmax) keep.push_back(i);
+  const int r = (int)keep.size();
+  if (r < 1 || r > 64 || 2 * r > Np) return GMM_OK;
+  // U [Np][r], V [r][Np]; check U V against S^ (the transposed ST holds S^)
+  std::vector<double> U((size_t)Np * r), V((size_t)r * Np);
+  for (int rho = 0; rho < r; ++rho) {
+    const int e = keep[rho];
+    const double lam = a[(size_t)e * Np + e];
+    for (int Q = 0; Q < Np; ++Q) {
+      U[(size_t)Q * r + rho] = q[(size_t)Q * Np + e] * lam;
+      V[(size_t)rho * Np + Q] = q[(size_t)Q * Np + e] * (pairs[Q].x == pairs[Q].y ? 1.0 : 2.0);
+    }
+  }
+  double err = 0, ref = 0;
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) {
+      double x = 0;
+      for (int rho = 0; rho < r; ++rho) x += U[(size_t)i * r + rho] * V[(size_t)rho * Np + j];
+      const double sh = ST[(size_t)j * P->rpad + i];
+      err = std::max(err, std::fabs(x - sh));
+      ref = std::max(ref, std::fabs(sh));
+    }
+  if (!(err <= 1e-12 * ref)) return GMM_OK;
+  const int rq = ((r + 15) / 16) * 16, kp = ((Np + 63) / 64) * 64;
+  std::vector<T> vt((size_t)kp * rq, T(0)), ut((size_t)64 * P->rpad, T(0));
+  for (int k = 0; k < Np; ++k)
+    for (int rho = 0; rho < r; ++rho) vt[(size_t)k * rq + rho] = (T)V[(size_t)rho * Np + k];
+  for (int rho = 0; rho < r; ++rho)
+    for (int row = 0; row < Np; ++row) ut[(size_t)rho * P->rpad + row] = (T)U[(size_t)row * r + rho];
+  int rc;
+  if ((rc = dev_alloc(&P->const_bytes, &P->VT, vt.size() * sizeof(T))) ||
+      (rc = dev_alloc(&P->const_bytes, &P->UT, ut.size() * sizeof(T))))
+    return rc;
+  GMM_HIP(hipMemcpy(P->VT, vt.data(), vt.size() * sizeof(T), hipMemcpyHostToDevice));
+  GMM_HIP(hipMemcpy(P->UT, ut.data(), ut.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (P->bf16) {
+    std::vector<uint16_t> hi((size_t)P->rpad * 64, 0), lo((size_t)P->rpad * 64, 0);
+    for (int row = 0; row < Np; ++row)
+      for (int rho = 0; rho < r; ++rho) {
+        const float x = (float)U[(size_t)row * r + rho];
+        const uint16_t h = host_bf16(x);
+        hi[(size_t)row * 64 + rho] = h;
+        lo[(size_t)row * 64 + rho] = host_bf16(x - host_bf16_value(h));
+      }
+    if ((rc = dev_alloc(&P->const_bytes, &P->Uhi, hi.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Ulo, lo.size() * 2)))
+      return rc;
+    GMM_HIP(hipMemcpy(P->Uhi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Ulo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+  }
+  P->factored = true;
+  P->rank = r;
+  P->rq = rq;
+  P->kp = kp;
+  return GMM_OK;
+}
+
 template <typename T>
 int build_raman(gmm_plan_s* P, const double* hR) {
   // weights h_R(k dt) normalised to unit sum; H = FFT_{+}(w); Hs = H / H[0] / Nt
@@ -456,7 +613,8 @@ int build_raman(gmm_plan_s* P, const double* hR) {
 void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
-  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, (void*)P->pidx, (void*)P->pairs, (void*)P->ctrl})
+  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, (void*)P->pidx,
+                  (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
   if (P->h_partials) (void)hipHostFree(P->h_partials);
@@ -482,6 +640,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (!(p->dt > 0) || !(p->omega0 > 0) || !(p->n2 >= 0) || !(p->fR >= 0 && p->fR <= 1))
     return fail(GMM_ERR_ARG, "dt, omega0 must be > 0; n2 >= 0; 0 <= fR <= 1");
   if (p->max_iter < 1 || p->fixed_iters < 0 || !(p->tol >= 0)) return fail(GMM_ERR_ARG, "bad iteration control");
+  if (p->factor_policy != 0 && p->factor_policy != 1) return fail(GMM_ERR_ARG, "factor_policy must be 0 or 1");
   const double domega = 2.0 * kPi / (nt * p->dt);
   if (p->self_steepening && !(p->omega0 - domega * (nt / 2) > 0))
     return fail(GMM_ERR_ARG, "1 + omega/omega0 <= 0 on the grid: window too fine for the shock term");
@@ -582,6 +741,10 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (raman) {
     rc = fp64 ? build_raman<double>(P, hR) : build_raman<float>(P, hR);
     if (rc) return bail(rc);
+    if (p->factor_policy == 0) {
+      rc = fp64 ? try_factor<double>(P, SK, pairs, ST) : try_factor<float>(P, SK, pairs, ST);
+      if (rc) return bail(rc);
+    }
   }
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
   if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
@@ -636,6 +799,8 @@ int gmm_plan_destroy(gmm_plan plan) {
 const char* gmm_last_error(void) { return g_last_error.c_str(); }
 
 long long gmm_plan_device_bytes(gmm_plan plan) { return plan ? plan->const_bytes + plan->ws_bytes : 0; }
+
+int gmm_plan_rank(gmm_plan plan) { return plan && plan->factored ? plan->rank : 0; }
 
 int gmm_profile_enable(gmm_plan plan, int kinds) {
   if (!plan) return fail(GMM_ERR_ARG, "null plan");

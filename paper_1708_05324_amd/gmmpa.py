@@ -29,15 +29,16 @@ GMM_FP32 = 1
 GMM_BF16X3 = 2
 
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_nonlinear", "gmm_plan_destroy", "gmm_last_error",
-           "gmm_plan_device_bytes", "gmm_profile_enable", "gmm_profile_read")
-PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close")
+           "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable", "gmm_profile_read")
+PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project")
 
 
 class gmm_params(ctypes.Structure):
     _fields_ = [("n_modes", ctypes.c_int), ("nt", ctypes.c_int), ("n_beta", ctypes.c_int),
                 ("dt", ctypes.c_double), ("omega0", ctypes.c_double), ("n2", ctypes.c_double),
                 ("fR", ctypes.c_double), ("self_steepening", ctypes.c_int), ("precision", ctypes.c_int),
-                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("factor_policy", ctypes.c_int)]
 
 
 class gmm_stats(ctypes.Structure):
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_last_error.restype = ctypes.c_char_p
     lib.gmm_plan_device_bytes.argtypes = [vp]
     lib.gmm_plan_device_bytes.restype = ctypes.c_longlong
+    lib.gmm_plan_rank.argtypes = [vp]
+    lib.gmm_plan_rank.restype = ci
     lib.gmm_profile_enable.argtypes = [vp, ci]
     lib.gmm_profile_enable.restype = ci
     lib.gmm_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_longlong), ci]
@@ -116,7 +119,7 @@ class Plan:
 
     def __init__(self, betas, SK, hR=None, *, nt: int, dt: float, omega0: float, n2: float, fR: float,
                  self_steepening: int = 1, precision: str = "fp64", tol: float = 1e-12, max_iter: int = 20,
-                 fixed_iters: int = 0, SR=None, stream=None):
+                 fixed_iters: int = 0, factor_policy: int = 0, SR=None, stream=None):
         import torch
         self.lib = load_library()
         betas = np.ascontiguousarray(np.atleast_2d(np.asarray(betas, dtype=np.float64)))
@@ -133,7 +136,7 @@ class Plan:
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
         prec = {"fp64": GMM_FP64, "fp32": GMM_FP32, "bf16x3": GMM_BF16X3}[precision]
         self.params = gmm_params(self.n_modes, nt, betas.shape[1], dt, omega0, n2, fR, int(self_steepening),
-                                 prec, tol, max_iter, fixed_iters)
+                                 prec, tol, max_iter, fixed_iters, factor_policy)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -198,6 +201,10 @@ class Plan:
         n = (ctypes.c_longlong * k)()
         _check(self.lib.gmm_profile_read(self.handle, ms, n, k))
         return {name: (ms[i], n[i]) for i, name in enumerate(PROFILE_KINDS)}
+
+    def rank(self) -> int:
+        """Rank of the coupling factor used (0: packed matrix)."""
+        return int(self.lib.gmm_plan_rank(self.handle))
 
     def device_bytes(self) -> int:
         return int(self.lib.gmm_plan_device_bytes(self.handle))

@@ -261,6 +261,16 @@ def config3(dz: float | None = None) -> Workload:
                          self_steepening=1, M=10, L=1.0, dz=dz, name="grin15_raman_nt16384")
 
 
+def fig3_workload() -> Workload:
+    """10 GRIN modes (groups 0-3), Nt = 2^14 over 40 ps, Kerr + Raman + shock, 200 fs
+    Gaussian of 100 nJ over the modes, dz = z_NL / 200 (the ratio the timing
+    comparison of the parallel algorithm quotes as typical)."""
+    w = grin_workload(4, 4, 2 ** 14, DT_FINE, "gaussian", 200e-15, energy=100e-9, fR=0.18,
+                      self_steepening=1, M=10, L=1.0, name="grin10_raman_nt16384")
+    w.dz = 1.0 / (w.extra["gamma0000"] * w.extra["P0"]) / 200.0
+    return w
+
+
 def random_fields(seed: int, n_modes: int, nt: int, scale: float = 1.0) -> np.ndarray:
     """Smooth-ish random complex fields [N][nt] for operator-level parity checks."""
     rng = np.random.default_rng(SEED_BASE + 1000 + seed)

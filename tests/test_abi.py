@@ -59,7 +59,7 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 def _params(**kw):
     base = dict(n_modes=3, nt=256, n_beta=3, dt=10e-15, omega0=synth.GrinFiber().omega0, n2=2.3e-20,
-                fR=0.0, self_steepening=0, precision=0, tol=1e-12, max_iter=20, fixed_iters=0)
+                fR=0.0, self_steepening=0, precision=0, tol=1e-12, max_iter=20, fixed_iters=0, factor_policy=0)
     base.update(kw)
     return gmmpa.gmm_params(**base)
 
@@ -86,6 +86,7 @@ def _create(lib, prm, S=None, hR=None, SR=None, betas=None):
     (dict(dt=0.0), gmmpa.GMM_ERR_ARG),
     (dict(fR=1.5), gmmpa.GMM_ERR_ARG),
     (dict(max_iter=0), gmmpa.GMM_ERR_ARG),
+    (dict(factor_policy=2), gmmpa.GMM_ERR_ARG),
     (dict(fR=0.18), gmmpa.GMM_ERR_ARG),                     # Raman without h_R
     (dict(self_steepening=1, dt=0.5e-15), gmmpa.GMM_ERR_ARG),   # 1 + w/w0 <= 0 on the grid
     (dict(n_modes=23, nt=256), gmmpa.GMM_ERR_UNSUPPORTED),  # beyond 256 packed rows
@@ -116,3 +117,4 @@ def test_null_arguments(lib):
     assert lib.gmm_nonlinear(None, None, 1, None) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_plan_destroy(None) == 0
     assert lib.gmm_plan_device_bytes(None) == 0
+    assert lib.gmm_plan_rank(None) == 0

@@ -196,3 +196,40 @@ def test_small_workloads_several_large_steps(torch_gpu, prec, cfg):
     print(f"[{prec} cfg{cfg}] error {err:.3e} iters gpu {res.stats['iterations']} oracle {sum(st.iterations)}",
           flush=True)
     assert err < {"fp64": 1e-8, "fp32": 2e-5, "bf16x3": 1e-3}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_rank_factor_route_matches_packed_route_and_oracle(torch_gpu, prec):
+    """15 HG modes: the packed coupling matrix has rank 45 (products H_a H_b span
+    the polynomials of degree <= 8 in x and y), so the Raman term is convolved in
+    the 45-dimensional factor space.  Both routes must match the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=5, nt=1024, fR=0.18, s=1, dt=20e-15)
+    m = O.model_from_workload(w)
+    ops = O._Ops(m, w.nt)
+    spectra = [O.to_spectrum(w.A0 + 0.3 * c * synth.random_fields(c, w.n_modes, w.nt, scale=100.0))
+               for c in range(2)]
+    ref = np.stack([ops.N(a) for a in spectra])
+    At = to_dev(torch, np.stack(spectra), prec)
+    factored = make_plan(w, prec, factor_policy=0)
+    packed = make_plan(w, prec, factor_policy=1)
+    assert factored.rank() == 45 and packed.rank() == 0
+    e1 = relmax(factored.nonlinear(At).cpu().numpy(), ref)
+    e2 = relmax(packed.nonlinear(At).cpu().numpy(), ref)
+    print(f"[{prec}] factored {e1:.2e} packed {e2:.2e}", flush=True)
+    assert e1 < TOL_OP[prec] and e2 < TOL_OP[prec]
+
+
+def test_full_rank_tensor_keeps_the_packed_route(torch_gpu):
+    """A random symmetric tensor has a full-rank packed matrix: no factor is used,
+    and the Raman path still matches the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=5, nt=512, fR=0.18, s=1, dt=40e-15)
+    w.S = synth.random_symmetric_tensor(5, w.n_modes) * w.S[0, 0, 0, 0]
+    m = O.model_from_workload(w)
+    ops = O._Ops(m, w.nt)
+    At = O.to_spectrum(w.A0)[None]
+    plan = make_plan(w, "fp64")
+    assert plan.rank() == 0
+    got = plan.nonlinear(to_dev(torch, At, "fp64")).cpu().numpy()
+    assert relmax(got, ops.N(At[0])[None]) < TOL_OP["fp64"]
