@@ -10,6 +10,8 @@
 // is A(t) = sum_k A~_k exp(-i w_k t), so the spectrum is (1/Nt) * FFT_{+}(A)
 // and the field is FFT_{-}(A~).
 #pragma once
+#include <type_traits>
+
 #include "gmm_fft.hpp"
 
 namespace gmm {
@@ -17,6 +19,8 @@ namespace gmm {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 // float -> bfloat16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -117,7 +121,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
   const bool has2 = Q2 < Np;
   const int2 a = pairs[Q1];
   const int2 b = has2 ? pairs[Q2] : a;
-  const bool share = b.x == a.x;  // consecutive pairs usually share their first mode
+  const bool share_m = b.x == a.x, share_n = b.y == a.y;  // consecutive pairs (m, n), (m + 1, n) share n
   const cplx<T>* Aj = A + (size_t)jj * N * S::N;
   const cplx<T>* am = Aj + (size_t)a.x * S::N;
   const cplx<T>* an = Aj + (size_t)a.y * S::N;
@@ -130,7 +134,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
     const cplx<T> x = am[t], y = an[t];
     T b2 = 0;
     if (has2) {
-      const cplx<T> u = share ? x : bm[t], w = bn[t];
+      const cplx<T> u = share_m ? x : bm[t], w = share_n ? y : bn[t];
       b2 = u.re * w.re + u.im * w.im;
     }
     z[i] = {x.re * y.re + x.im * y.im, b2};
@@ -173,7 +177,7 @@ __global__ __launch_bounds__((FftShape<LOGN, 4>::THREADS)) void k_pairs_bf16(
   const bool has2 = Q2 < Np;
   const int2 a = pairs[Q1];
   const int2 b = has2 ? pairs[Q2] : a;
-  const bool share = b.x == a.x;
+  const bool share_m = b.x == a.x, share_n = b.y == a.y;  // consecutive pairs (m, n), (m + 1, n) share n
   const cplx<float>* Aj = A + (size_t)jj * N * S::N;
   const cplx<float>* am = Aj + (size_t)a.x * S::N;
   const cplx<float>* an = Aj + (size_t)a.y * S::N;
@@ -186,7 +190,7 @@ __global__ __launch_bounds__((FftShape<LOGN, 4>::THREADS)) void k_pairs_bf16(
     const cplx<float> x = am[t], y = an[t];
     float b2 = 0.f;
     if (has2) {
-      const cplx<float> u = share ? x : bm[t], w = bn[t];
+      const cplx<float> u = share_m ? x : bm[t], w = share_n ? y : bn[t];
       b2 = u.re * w.re + u.im * w.im;
     }
     z[i] = {x.re * y.re + x.im * y.im, b2};
@@ -562,6 +566,184 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
 }
 
 // ---------------------------------------------------------------------------
+// Column-owner contraction for the rank-r route: C = U Y' (K = 64 factor
+// columns, Rpad = 32, 64 or 128 pair rows), then NL_p(t) = sum_l C_(p,l)(t) A_l(t).
+// Pairs are numbered in triangular order Q = l (l + 1) / 2 + p (p <= l), so a
+// row index fixes its mode pair whatever N is, and the projection is unrolled
+// with compile-time mode indices over the LMAX modes whose pairs fit in RPAD
+// rows: rows beyond Np are zero rows of U, and the field values of modes
+// l >= N are held at zero, so they add nothing.
+// Each wave owns one 64-column tile at a time (persistent over tiles).  It
+// keeps A_l(t) and the partial sums NL_p(t) of its columns in registers, one
+// column per lane, forms C 16 rows at a time on MFMA, passes those rows through
+// its own LDS slab (transposed, so that each lane reads its column as 16-byte
+// vectors) and folds them into NL.  After the factor U has been staged in LDS
+// the waves never wait for each other.
+//   BF16: U and Y' as hi/lo planes; v_mfma_f32_16x16x32_bf16, products
+//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  Y' planes [count][8][Nt][8].
+//   FP32: v_mfma_f32_16x16x4f32.  Y' [count][kv][Nt], rows clamped to kv - 1
+//         (U is zero there).
+__host__ __device__ constexpr int tri_mode_l(int Q) {
+  int l = 0;
+  while ((l + 1) * (l + 2) / 2 <= Q) ++l;
+  return l;
+}
+__host__ __device__ constexpr int tri_mode_p(int Q) { return Q - tri_mode_l(Q) * (tri_mode_l(Q) + 1) / 2; }
+
+// A wave-uniform pointer pinned to scalar registers: indexing it with a 32-bit
+// lane offset then addresses memory as SGPR base + VGPR offset, instead of one
+// 64-bit VGPR address per row kept alive between a load and a later store.
+template <typename P>
+__device__ __forceinline__ P* sgpr_ptr(P* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int RPAD, bool BF16>
+struct ColShape {
+  static_assert(RPAD == 32 || RPAD == 64 || RPAD == 128, "pair rows padded to 32, 64 or 128");
+  static constexpr int K = 64;
+  static constexpr int GROUPS = RPAD / 16;              // 16 rows of C per MFMA pass
+  static constexpr int LMAX = tri_mode_l(RPAD);        // most modes whose pairs fit in RPAD rows
+  static constexpr int NP_MAX = LMAX * (LMAX + 1) / 2;  // rows beyond are padding (zero rows of U)
+  static constexpr int SLAB = 20;                       // floats per column of a wave's C slab (16 + pad)
+  // U: BF16 [2][RPAD][9] 16-byte chunks (one pad chunk per row); FP32 [K][RPAD + 16]
+  static constexpr size_t u_bytes() { return BF16 ? (size_t)2 * RPAD * 9 * 16 : (size_t)K * (RPAD + 16) * 4; }
+  static constexpr size_t lds_bytes() { return u_bytes() + (size_t)4 * 64 * SLAB * 4; }
+};
+
+template <int RPAD, bool BF16>
+__global__ __launch_bounds__(256, 2) void k_contract_cols(
+    const void* __restrict__ Ua, const void* __restrict__ Ub, const void* __restrict__ Ya,
+    const void* __restrict__ Yb, cplx<float>* A_NL, int N, int kv, int Nt, int ntiles, const Ctrl* ctrl) {
+  using CS = ColShape<RPAD, BF16>;
+  constexpr int LMAX = CS::LMAX, SLAB = CS::SLAB, K = CS::K;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  float* slab = reinterpret_cast<float*>(smem_raw + CS::u_bytes()) + wave * 64 * SLAB;
+  if constexpr (BF16) {
+    uint4* sU = reinterpret_cast<uint4*>(smem_raw);
+    const uint4* uh = reinterpret_cast<const uint4*>(Ua);
+    const uint4* ul = reinterpret_cast<const uint4*>(Ub);
+    for (int i = tid; i < 2 * RPAD * 8; i += 256) {
+      const int plane = i / (RPAD * 8), r = (i / 8) % RPAD, c = i % 8;
+      sU[(plane * RPAD + r) * 9 + c] = (plane ? ul : uh)[r * 8 + c];
+    }
+  } else {
+    float* sU = reinterpret_cast<float*>(smem_raw);
+    const float* ut = reinterpret_cast<const float*>(Ua);
+    for (int i = tid; i < K * RPAD; i += 256) sU[(i / RPAD) * (RPAD + 16) + i % RPAD] = ut[i];
+  }
+  __syncthreads();
+  const int tiles_per_j = Nt / 64;
+  for (int tile_v = blockIdx.x * 4 + wave; tile_v < ntiles; tile_v += gridDim.x * 4) {
+    // wave-uniform tile: row bases stay in scalar registers, one lane offset in a vector register
+    const int tile = __builtin_amdgcn_readfirstlane(tile_v);
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * 64;
+    cplx<float>* Aj = A_NL + (size_t)jj * N * Nt + t0;
+    // operand B (Y') of the whole tile, straight from HBM
+    bf16x8 yh[BF16 ? 4 : 1][2], yl[BF16 ? 4 : 1][2];
+    float yf[BF16 ? 1 : 4][BF16 ? 1 : 16];
+    if constexpr (BF16) {
+      const uint4* ph = reinterpret_cast<const uint4*>(Ya) + (size_t)jj * 8 * Nt + t0 + lr;
+      const uint4* pl = reinterpret_cast<const uint4*>(Yb) + (size_t)jj * 8 * Nt + t0 + lr;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const size_t o = (size_t)(4 * ks + lk) * Nt + cb * 16;
+          yh[cb][ks] = __builtin_bit_cast(bf16x8, ph[o]);
+          yl[cb][ks] = __builtin_bit_cast(bf16x8, pl[o]);
+        }
+    } else {
+      const float* py = reinterpret_cast<const float*>(Ya) + (size_t)jj * kv * Nt + t0 + lr;
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int k = min(4 * ks + lk, kv - 1);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) yf[cb][ks] = py[(size_t)k * Nt + cb * 16];
+      }
+    }
+    const unsigned col = lane;  // 32-bit lane offset on a wave-uniform row base
+    cplx<float> a[LMAX], nl[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      a[l] = l < N ? sgpr_ptr(Aj + (size_t)l * Nt)[col] : cplx<float>{0.f, 0.f};
+      nl[l] = cplx<float>{0.f, 0.f};
+    }
+    static_for<0, CS::GROUPS>([&](auto gc) {
+      constexpr int G = decltype(gc)::value;  // rows 16 G .. 16 G + 15
+      if constexpr (16 * G < CS::NP_MAX) {
+        floatx4 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (BF16) {
+          const uint4* sU = reinterpret_cast<const uint4*>(smem_raw);
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks) {
+            const int r = 16 * G + lr;
+            const bf16x8 uh = __builtin_bit_cast(bf16x8, sU[r * 9 + 4 * ks + lk]);
+            const bf16x8 ul = __builtin_bit_cast(bf16x8, sU[(RPAD + r) * 9 + 4 * ks + lk]);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yh[cb][ks], acc[cb], 0, 0, 0);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yl[cb][ks], acc[cb], 0, 0, 0);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul, yh[cb][ks], acc[cb], 0, 0, 0);
+            }
+          }
+        } else {
+          const float* sU = reinterpret_cast<const float*>(smem_raw);
+#pragma unroll
+          for (int ks = 0; ks < 16; ++ks) {
+            const float u = sU[(4 * ks + lk) * (RPAD + 16) + 16 * G + lr];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(u, yf[cb][ks], acc[cb], 0, 0, 0);
+          }
+        }
+        // accumulator register i of lane (lr, lk) holds row 4 lk + i of column lr
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          *reinterpret_cast<floatx4*>(slab + (cb * 16 + lr) * SLAB + 4 * lk) = acc[cb];
+        __builtin_amdgcn_wave_barrier();
+        static_for<0, 4>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          const floatx4 v = *reinterpret_cast<const floatx4*>(slab + lane * SLAB + 4 * m);
+          static_for<0, 4>([&](auto ic) {
+            constexpr int Q = 16 * G + 4 * m + decltype(ic)::value;
+            if constexpr (Q < CS::NP_MAX) {
+              constexpr int l = tri_mode_l(Q), p = tri_mode_p(Q);
+              const float x = v[decltype(ic)::value];
+              nl[p].re += x * a[l].re;
+              nl[p].im += x * a[l].im;
+              if constexpr (p != l) {
+                nl[l].re += x * a[p].re;
+                nl[l].im += x * a[p].im;
+              }
+            }
+          });
+        });
+        __builtin_amdgcn_wave_barrier();
+      }
+    });
+#pragma unroll
+    for (int p = 0; p < LMAX; ++p)
+      if (p < N) sgpr_ptr(Aj + (size_t)p * Nt)[col] = nl[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Rank-r route for the Raman term.  The packed matrix factors as S^ = U V
 // (U: Np x r, V: r x Np, from the eigen-decomposition of the symmetric pair
 // matrix; r = its numerical rank).  The blended Raman filter g acts on time and
@@ -618,6 +800,159 @@ __global__ __launch_bounds__(256) void k_project(
     for (int r = 0; r < RTQ; ++r)
 #pragma unroll
       for (int i = 0; i < 4; ++i) Yj[(size_t)(r * 16 + Mfma<T>::out_row(lk, i)) * Nt] = acc[r][i];
+  }
+}
+
+// Column-owner projection Y = V B for the rank-r route (complex64 fields):
+// each wave owns one 64-column tile at a time (persistent), holds A_l(t) of its
+// columns in registers (one column per lane) and forms the pair products
+// B_Q(t) = Re(A_m A_n^*) 32 pairs at a time with compile-time mode indices
+// (triangular pair order; pairs beyond Np are zero).  A chunk goes through the
+// wave's own LDS slab, transposed into MFMA operand layout, and is multiplied
+// by V (staged in LDS once per block).  Y [count][RQ][Nt] in FP32.
+//   BF16: B and V split as hi + lo, v_mfma_f32_16x16x32_bf16, products
+//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  V hi/lo [RQ][KPAD] bf16.
+//   FP32: v_mfma_f32_16x16x4f32.  V^T [KPAD][RQ].
+template <int RQ, int KPAD, bool BF16>
+struct ProjShape {
+  static_assert(RQ % 16 == 0 && RQ <= 64 && (KPAD == 64 || KPAD == 128), "projection shape");
+  static constexpr int RB = RQ / 16;
+  static constexpr int CHUNKS = KPAD / 32;
+  static constexpr int LMAX = tri_mode_l(KPAD);
+  static constexpr int NP_MAX = LMAX * (LMAX + 1) / 2;
+  static constexpr int VS = BF16 ? KPAD / 8 + 1 : (RQ <= 16 ? 16 : 80);  // V row stride (16-byte chunks | floats)
+  static constexpr int SS = BF16 ? 5 : 36;  // slab stride per column (16-byte chunks per plane | floats)
+  static constexpr size_t v_bytes() { return BF16 ? (size_t)2 * RQ * VS * 16 : (size_t)KPAD * VS * 4; }
+  static constexpr size_t slab_bytes() { return BF16 ? (size_t)2 * 64 * SS * 16 : (size_t)64 * SS * 4; }
+  static constexpr size_t lds_bytes() { return v_bytes() + 4 * slab_bytes(); }
+};
+
+template <int RQ, int KPAD, bool BF16>
+__global__ __launch_bounds__(256, 2) void k_project_cols(
+    const void* __restrict__ Va, const void* __restrict__ Vb, const cplx<float>* __restrict__ A,
+    float* __restrict__ Y, int N, int Nt, int ntiles, const Ctrl* ctrl) {
+  using PS = ProjShape<RQ, KPAD, BF16>;
+  constexpr int RB = PS::RB, LMAX = PS::LMAX, VS = PS::VS, SS = PS::SS;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  unsigned char* slab = smem_raw + PS::v_bytes() + wave * PS::slab_bytes();
+  if constexpr (BF16) {
+    uint4* sV = reinterpret_cast<uint4*>(smem_raw);
+    const uint4* vh = reinterpret_cast<const uint4*>(Va);
+    const uint4* vl = reinterpret_cast<const uint4*>(Vb);
+    constexpr int KC = KPAD / 8;
+    for (int i = tid; i < 2 * RQ * KC; i += 256) {
+      const int plane = i / (RQ * KC), r = (i / KC) % RQ, c = i % KC;
+      sV[(plane * RQ + r) * VS + c] = (plane ? vl : vh)[r * KC + c];
+    }
+  } else {
+    float* sV = reinterpret_cast<float*>(smem_raw);
+    const float* vt = reinterpret_cast<const float*>(Va);
+    for (int i = tid; i < KPAD * RQ; i += 256) sV[(i / RQ) * VS + i % RQ] = vt[i];
+  }
+  __syncthreads();
+  const int tiles_per_j = Nt / 64;
+  const unsigned col = lane;
+  for (int tile_v = blockIdx.x * 4 + wave; tile_v < ntiles; tile_v += gridDim.x * 4) {
+    const int tile = __builtin_amdgcn_readfirstlane(tile_v);
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * 64;
+    const cplx<float>* Aj = A + (size_t)jj * N * Nt + t0;
+    cplx<float> a[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) a[l] = l < N ? sgpr_ptr(Aj + (size_t)l * Nt)[col] : cplx<float>{0.f, 0.f};
+    floatx4 acc[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    static_for<0, PS::CHUNKS>([&](auto cc) {
+      constexpr int C = decltype(cc)::value;  // pairs 32 C .. 32 C + 31
+      if constexpr (32 * C < PS::NP_MAX) {
+        float x[32];
+        static_for<0, 32>([&](auto qc) {
+          constexpr int Q = 32 * C + decltype(qc)::value;
+          if constexpr (Q < PS::NP_MAX) {
+            constexpr int n = tri_mode_l(Q), m = tri_mode_p(Q);
+            x[decltype(qc)::value] = a[m].re * a[n].re + a[m].im * a[n].im;
+          } else {
+            x[decltype(qc)::value] = 0.f;
+          }
+        });
+        if constexpr (BF16) {
+          // this lane's column: 32 pairs as 4 chunks of 8 bf16 per plane
+          uint4* sl = reinterpret_cast<uint4*>(slab);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const floatx2 v = {x[8 * j + 2 * e], x[8 * j + 2 * e + 1]};
+              const bf16x2 hv = __builtin_convertvector(v, bf16x2);
+              const floatx2 hf = __builtin_convertvector(hv, floatx2);
+              const bf16x2 lv = __builtin_convertvector(floatx2{v[0] - hf[0], v[1] - hf[1]}, bf16x2);
+              h[e] = __builtin_bit_cast(uint32_t, hv);
+              l[e] = __builtin_bit_cast(uint32_t, lv);
+            }
+            sl[lane * SS + j] = uint4{h[0], h[1], h[2], h[3]};
+            sl[(64 + lane) * SS + j] = uint4{l[0], l[1], l[2], l[3]};
+          }
+          __builtin_amdgcn_wave_barrier();
+          const uint4* sV = reinterpret_cast<const uint4*>(smem_raw);
+          bf16x8 vh[RB], vl[RB];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            vh[rb] = __builtin_bit_cast(bf16x8, sV[(rb * 16 + lr) * VS + 4 * C + lk]);
+            vl[rb] = __builtin_bit_cast(bf16x8, sV[(RQ + rb * 16 + lr) * VS + 4 * C + lk]);
+          }
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const bf16x8 bh = __builtin_bit_cast(bf16x8, sl[(cb * 16 + lr) * SS + lk]);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, sl[(64 + cb * 16 + lr) * SS + lk]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[rb], bh, acc[rb][cb], 0, 0, 0);
+              acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[rb], bl, acc[rb][cb], 0, 0, 0);
+              acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl[rb], bh, acc[rb][cb], 0, 0, 0);
+            }
+          }
+        } else {
+          float* sl = reinterpret_cast<float*>(slab);
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            *reinterpret_cast<floatx4*>(sl + lane * SS + 4 * j) =
+                floatx4{x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]};
+          __builtin_amdgcn_wave_barrier();
+          const float* sV = reinterpret_cast<const float*>(smem_raw);
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            float v[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) v[rb] = sV[(32 * C + 4 * ks + lk) * VS + rb * 16 + lr];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+              const float b = sl[(cb * 16 + lr) * SS + 4 * ks + lk];
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[rb], b, acc[rb][cb], 0, 0, 0);
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    });
+    // accumulator register i of lane (lr, lk) holds row 4 lk + i of column lr
+    float* Yj = Y + (size_t)jj * RQ * Nt + t0;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float* yrow = sgpr_ptr(Yj + (size_t)(rb * 16 + i) * Nt);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) yrow[(unsigned)(4 * lk) * Nt + cb * 16 + lr] = acc[rb][cb][i];
+      }
   }
 }
 

@@ -46,6 +46,16 @@ hipError_t launch_pairs_bf16(int logn, bool raman, const cplx<float>* A, uint32_
 hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* Slo, const uint32_t* Bhi,
                                 const uint32_t* Blo, cplx<float>* A_NL, const int* pidx, int N, int Nt, int count,
                                 const Ctrl* ctrl, hipStream_t s);
+// Column-owner contraction of the rank-r route (complex64 fields, Rpad 64 or 128,
+// K = 64): BF16 split (Ua/Ub = U hi/lo [Rpad][64] bf16, Ya/Yb = Y' planes) or
+// FP32 (Ua = U^T [64][Rpad], Ya = Y' [count][kv][Nt]).
+hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
+                                cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
+                                hipStream_t s);
+// Column-owner projection Y = V B of the rank-r route (complex64 fields, RQ <= 64,
+// KPAD 64 or 128): BF16 split (Va/Vb = V hi/lo [RQ][KPAD] bf16) or FP32 (Va = V^T [KPAD][RQ]).
+hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, const void* Vb, const cplx<float>* A,
+                               float* Y, int N, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 

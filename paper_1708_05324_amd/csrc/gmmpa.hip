@@ -4,6 +4,7 @@
 // in FP64, owns device memory, and sequences the kernels of each large step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -154,6 +155,8 @@ struct gmm_plan_s {
   void* UT = nullptr;      // [64][rpad] U transposed (contraction operand, K = 64)
   void* Uhi = nullptr;     // [rpad][64] bf16 split of U, K contiguous (BF16X3)
   void* Ulo = nullptr;
+  void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
+  void* Vlo = nullptr;
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
@@ -198,7 +201,9 @@ size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->e
 // B' for `cap` sub-steps: [cap][Np][Nt] reals, or two bf16 planes [cap][Kpad/8][Nt][8].
 size_t bp_bytes(const gmm_plan_s* P, int cap) {
   if (P->bf16) return 2 * (size_t)cap * gmm::kBf16Kpad * P->nt * 2;
-  return (size_t)cap * P->Np * P->nt * P->esz;
+  // packed route: [cap][Np][Nt]; rank-r route: Y' [cap][RQ][Nt] (RQ can exceed Np for small Np)
+  const int rows = P->factored ? std::max(P->Np, P->rq) : P->Np;
+  return (size_t)cap * rows * P->nt * P->esz;
 }
 size_t bp_plane_words(const gmm_plan_s* P) { return (size_t)P->cap * gmm::kBf16Kpad * P->nt / 2; }
 
@@ -247,8 +252,14 @@ struct Runner {
                                      tw(), ctrl, P->stream));
     if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
       T* Y = (T*)P->Y;
-      GMM_LAUNCH(P, GMM_PROF_PROJECT, Launch<T>::project(P->rq, P->kp, (const T*)P->VT, W, Y, P->pairs, P->N, P->Np,
-                                                       P->nt, count, ctrl, P->stream));
+      if constexpr (std::is_same<T, float>::value) {
+        GMM_LAUNCH(P, GMM_PROF_PROJECT,
+                   gmm::launch_project_cols(P->rq, P->kp, P->bf16, P->bf16 ? P->Vhi : P->VT, P->Vlo, W, Y, P->N,
+                                            P->nt, count, ctrl, P->stream));
+      } else {
+        GMM_LAUNCH(P, GMM_PROF_PROJECT, Launch<T>::project(P->rq, P->kp, (const T*)P->VT, W, Y, P->pairs, P->N,
+                                                         P->Np, P->nt, count, ctrl, P->stream));
+      }
       const int R = P->rank + (P->rank & 1);
       if constexpr (std::is_same<T, float>::value) {
         if (P->bf16) {
@@ -256,15 +267,20 @@ struct Runner {
           uint32_t* blo = bhi + bp_plane_words(P);
           GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
                                                               (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
-          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, 64, P->Uhi, P->Ulo, bhi, blo, W,
-                                                                     P->pidx, P->N, P->nt, count, ctrl, P->stream));
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
+                                                                     P->N, P->rq, P->nt, count, ctrl, P->stream));
         }
       }
       if (!P->bf16) {
         GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
                                                       (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
-        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)P->Bp, W, P->pidx,
-                                                             P->N, P->rq, P->nt, count, ctrl, P->stream));
+        if constexpr (std::is_same<T, float>::value) {
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, P->Bp, nullptr,
+                                                                     W, P->N, P->rq, P->nt, count, ctrl, P->stream));
+        } else {
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)P->Bp, W,
+                                                               P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream));
+        }
       }
     } else if constexpr (std::is_same<T, float>::value) {
       if (P->bf16) {
@@ -578,6 +594,19 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
       return rc;
     GMM_HIP(hipMemcpy(P->Uhi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
     GMM_HIP(hipMemcpy(P->Ulo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+    std::vector<uint16_t> vh((size_t)rq * kp, 0), vl((size_t)rq * kp, 0);
+    for (int rho = 0; rho < r; ++rho)
+      for (int Q = 0; Q < Np; ++Q) {
+        const float x = (float)V[(size_t)rho * Np + Q];
+        const uint16_t h = host_bf16(x);
+        vh[(size_t)rho * kp + Q] = h;
+        vl[(size_t)rho * kp + Q] = host_bf16(x - host_bf16_value(h));
+      }
+    if ((rc = dev_alloc(&P->const_bytes, &P->Vhi, vh.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Vlo, vl.size() * 2)))
+      return rc;
+    GMM_HIP(hipMemcpy(P->Vhi, vh.data(), vh.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Vlo, vl.data(), vl.size() * 2, hipMemcpyHostToDevice));
   }
   P->factored = true;
   P->rank = r;
@@ -613,7 +642,8 @@ int build_raman(gmm_plan_s* P, const double* hR) {
 void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
-  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, (void*)P->pidx,
+  for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
+                  (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
@@ -711,11 +741,11 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if ((rc = dev_alloc(&P->const_bytes, &P->coef, coef.size() * sizeof(double)))) return bail(rc);
   if (hipMemcpy(P->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(GMM_ERR_HIP, "copy of dispersion coefficients failed"));
-  // mode pairs (m <= n, lexicographic) and pair index table
+  // mode pairs (m <= n) in triangular order Q = n (n + 1) / 2 + m, and the pair index table
   std::vector<int2> pairs;
   std::vector<int> pidx((size_t)N * N);
-  for (int m = 0; m < N; ++m)
-    for (int n = m; n < N; ++n) {
+  for (int n = 0; n < N; ++n)
+    for (int m = 0; m <= n; ++m) {
       pidx[(size_t)m * N + n] = pidx[(size_t)n * N + m] = (int)pairs.size();
       pairs.push_back(make_int2(m, n));
     }
