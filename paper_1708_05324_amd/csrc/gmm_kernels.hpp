@@ -22,13 +22,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
 
-// float -> bfloat16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
+// Split of two floats into packed bfloat16 pairs x = hi + lo: hi = bf16(x),
+// lo = bf16(x - hi), both rounded to nearest even by v_cvt_pk_bf16_f32.
+// Element 0 lands in the low 16 bits of each word.
+__device__ __forceinline__ void bf16_split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const bf16x2 h = __builtin_convertvector(floatx2{x0, x1}, bf16x2);
+  const floatx2 hf = __builtin_convertvector(h, floatx2);
+  const bf16x2 l = __builtin_convertvector(floatx2{x0 - hf[0], x1 - hf[1]}, bf16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
 }
-__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
 
 // Workgroups are dealt to the 8 XCDs round-robin by id.  For a 1-D grid of
 // 8 * G blocks, block b runs on XCD b % 8; numbering work items
@@ -69,26 +72,43 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_f
 }
 
 // ---------------------------------------------------------------------------
-// a1: A_j(t) = FFT_{-}[ exp(D_w z_j) psi_j ],  z_j = (j0 + jj) * dz.
+// Dispersion phase table E[j][p][k] = exp(i (beta_p(w_k) - beta_0) z_j),
+// z_j = j dz, j = 0 .. rows - 1: the FP64 phase is folded into [-pi, pi] and
+// evaluated once per plan and step size; the iterated kernels read it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phase_table(cplx<T>* __restrict__ E, const double* __restrict__ coef,
+                                                     int nb, int N, int nt, long total, double dz, double domega) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long row = e / nt;
+  const int k = (int)(e - row * nt), p = (int)(row % N), j = (int)(row / N);
+  E[e] = expi_reduced<T>(disp_phase(coef + p * nb, nb, omega_of(k, nt, domega)) * ((double)j * dz));
+}
+
+// a1: A_j(t) = FFT_{-}[ exp(D_w z_j) psi_j ],  z_j = (j0 + jj) dz, the factor
+// read from the phase table (E = nullptr: no phase, z = 0).
 // grid (N, count); psi row (jj, p) at psi + (jj * psi_jrows + p) * Nt, where
 // psi_jrows is a row count: N for one field per sub-step, 0 to reuse psi_0.
 template <typename T, int LOGN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
-    const cplx<T>* __restrict__ psi, long psi_jrows, cplx<T>* __restrict__ A, const double* __restrict__ coef,
-    int nb, int j0, double dz, double domega, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+    const cplx<T>* __restrict__ psi, long psi_jrows, cplx<T>* __restrict__ A, const cplx<T>* __restrict__ E, int j0,
+    const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
   const cplx<T>* src = psi + ((size_t)jj * psi_jrows + p) * S::N;
-  const double z = (double)(j0 + jj) * dz;
-  const double* cp = coef + p * nb;
   cplx<T> v[S::R];
+  if (E != nullptr) {
+    const cplx<T>* ph = E + ((size_t)(j0 + jj) * N + p) * S::N;
 #pragma unroll
-  for (int i = 0; i < S::R; ++i) {
-    const int k = tid + i * S::THREADS;
-    cplx<T> e = expi_reduced<T>(disp_phase(cp, nb, omega_of(k, S::N, domega)) * z);
-    v[i] = cmul(src[k], e);
+    for (int i = 0; i < S::R; ++i) {
+      const int k = tid + i * S::THREADS;
+      v[i] = cmul(src[k], ph[k]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) v[i] = src[tid + i * S::THREADS];
   }
   block_fft<S, T, -1>(v, lds, tid, tw);
   cplx<T>* dst = A + ((size_t)jj * N + p) * S::N;
@@ -206,11 +226,10 @@ __global__ __launch_bounds__((FftShape<LOGN, 4>::THREADS)) void k_pairs_bf16(
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int t = tid + i * S::THREADS;
-    const uint32_t h1 = bf16_bits(z[i].re), h2 = has2 ? bf16_bits(z[i].im) : 0u;
-    const uint32_t l1 = bf16_bits(z[i].re - bf16_value(h1));
-    const uint32_t l2 = has2 ? bf16_bits(z[i].im - bf16_value(h2)) : 0u;
-    Bhi[base + (size_t)t * 4] = h1 | (h2 << 16);
-    Blo[base + (size_t)t * 4] = l1 | (l2 << 16);
+    uint32_t h, l;
+    bf16_split2(z[i].re, has2 ? z[i].im : 0.f, h, l);
+    Bhi[base + (size_t)t * 4] = h;
+    Blo[base + (size_t)t * 4] = l;
   }
 }
 
@@ -888,14 +907,7 @@ __global__ __launch_bounds__(256, 2) void k_project_cols(
           for (int j = 0; j < 4; ++j) {
             uint32_t h[4], l[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const floatx2 v = {x[8 * j + 2 * e], x[8 * j + 2 * e + 1]};
-              const bf16x2 hv = __builtin_convertvector(v, bf16x2);
-              const floatx2 hf = __builtin_convertvector(hv, floatx2);
-              const bf16x2 lv = __builtin_convertvector(floatx2{v[0] - hf[0], v[1] - hf[1]}, bf16x2);
-              h[e] = __builtin_bit_cast(uint32_t, hv);
-              l[e] = __builtin_bit_cast(uint32_t, lv);
-            }
+            for (int e = 0; e < 4; ++e) bf16_split2(x[8 * j + 2 * e], x[8 * j + 2 * e + 1], h[e], l[e]);
             sl[lane * SS + j] = uint4{h[0], h[1], h[2], h[3]};
             sl[(64 + lane) * SS + j] = uint4{l[0], l[1], l[2], l[3]};
           }
@@ -988,11 +1000,10 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_c
 #pragma unroll
     for (int i = 0; i < S::R; ++i) {
       const int t = tid + i * S::THREADS;
-      const uint32_t h1 = bf16_bits((float)z[i].re), h2 = bf16_bits((float)z[i].im);
-      const uint32_t l1 = bf16_bits((float)z[i].re - bf16_value(h1));
-      const uint32_t l2 = bf16_bits((float)z[i].im - bf16_value(h2));
-      Bhi[base + (size_t)t * 4] = h1 | (h2 << 16);
-      Blo[base + (size_t)t * 4] = l1 | (l2 << 16);
+      uint32_t h, l;
+      bf16_split2((float)z[i].re, (float)z[i].im, h, l);
+      Bhi[base + (size_t)t * 4] = h;
+      Blo[base + (size_t)t * 4] = l;
     }
   } else {
     T* o1 = Yout + ((size_t)jj * RQ + r1) * S::N;
@@ -1008,11 +1019,12 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_c
 
 // ---------------------------------------------------------------------------
 // a6: I_j(w) = exp(-D_w z_j) * i gamma^ (1 + s w/w0) * F{NL_j}(w),
-// F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt.  grid (N, count); in may alias out.
+// F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt; exp(-D_w z_j) = conj(E[j0 + jj])
+// (E = nullptr: z = 0).  grid (N, count); in may alias out.
 template <typename T, int LOGN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_spectral_out(
-    const cplx<T>* in, cplx<T>* out, const double* __restrict__ coef, int nb, int j0, double dz, double domega,
-    double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+    const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ E, int j0, double domega, double gscale,
+    double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
@@ -1022,15 +1034,16 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_s
 #pragma unroll
   for (int i = 0; i < S::R; ++i) v[i] = in[row + tid + i * S::THREADS];
   block_fft<S, T, +1>(v, lds, tid, tw);
-  const double z = (double)(j0 + jj) * dz;
-  const double* cp = coef + p * nb;
+  const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int k = tid + i * S::THREADS;
-    const double w = omega_of(k, S::N, domega);
-    const T f = (T)(gscale * (shock ? 1.0 + w * inv_omega0 : 1.0));
-    cplx<T> e = expi_reduced<T>(-disp_phase(cp, nb, w) * z);
-    cplx<T> x = cmul(v[i], e);
+    const T f = (T)(gscale * (shock ? 1.0 + omega_of(k, S::N, domega) * inv_omega0 : 1.0));
+    cplx<T> x = v[i];
+    if (ph != nullptr) {
+      const cplx<T> e = ph[k];
+      x = cmul(x, cplx<T>{e.re, -e.im});
+    }
     out[row + k] = cplx<T>{-f * x.im, f * x.re};
   }
 }
@@ -1084,16 +1097,13 @@ __global__ __launch_bounds__(256) void k_trapz(
   }
 }
 
-// a9: psi0 <- exp(D_w z) * src (element-wise over [N][Nt]).
+// a9: psi0 <- exp(D_w z_m) * src (element-wise over [N][Nt]); Em = E[m].
 template <typename T>
 __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
-                                                const double* __restrict__ coef, int nb, int nt, long nn, double z,
-                                                double domega) {
+                                                const cplx<T>* __restrict__ Em, long nn) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= nn) return;
-  const int p = (int)(e / nt), k = (int)(e - (long)p * nt);
-  const cplx<T> x = src[e];
-  dst[e] = cmul(x, expi_reduced<T>(disp_phase(coef + p * nb, nb, omega_of(k, nt, domega)) * z));
+  dst[e] = cmul(src[e], Em[e]);
 }
 
 // FP64 spectral sums for the bookkeeping: sum |A~|^2 and sum |A~|^2 / (w0 + w).

@@ -14,9 +14,11 @@ struct Launch {
   static bool supports_logn(int logn);
   static hipError_t fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* out, T scale, int rows,
                              const cplx<T>* tw, hipStream_t s);
-  static hipError_t phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const double* coef,
-                                  int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
-                                  const Ctrl* ctrl, hipStream_t s);
+  // E[j][p][k] = exp(i (beta_p(w_k) - beta_0) j dz), j < rows
+  static hipError_t phase_table(cplx<T>* E, const double* coef, int nb, int N, int nt, int rows, double dz,
+                                double domega, hipStream_t s);
+  static hipError_t phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E, int N,
+                                  int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
                           int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   // kpad = 0: packed matrix with K = Rpad (kv = Np rows per sub-step); kpad = 64: rank factor U (kv = RQ).
@@ -26,13 +28,12 @@ struct Launch {
                             int Nt, int count, const Ctrl* ctrl, hipStream_t s);
   static hipError_t conv(int logn, const T* Y, T* Yout, int R, int RQ, int count, const cplx<T>* Gs,
                          const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
-  static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
-                                 int count, int j0, double dz, double domega, double gscale, double inv_omega0,
-                                 int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const cplx<T>* E, int N, int count,
+                                 int j0, double domega, double gscale, double inv_omega0, int shock,
+                                 const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
-  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const double* coef, int nb, int nt, long nn, double z,
-                          double domega, hipStream_t s);
+  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s);
   static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
                               hipStream_t s);
   static hipError_t finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s);

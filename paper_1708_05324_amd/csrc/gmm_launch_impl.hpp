@@ -49,13 +49,21 @@ hipError_t Launch<T>::fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* o
 }
 
 template <typename T>
-hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const double* coef,
-                                    int nb, int N, int count, int j0, double dz, double domega, const cplx<T>* tw,
-                                    const Ctrl* ctrl, hipStream_t s) {
+hipError_t Launch<T>::phase_table(cplx<T>* E, const double* coef, int nb, int N, int nt, int rows, double dz,
+                                  double domega, hipStream_t s) {
+  const long total = (long)rows * N * nt;
+  hipLaunchKernelGGL((k_phase_table<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, E, coef, nb, N, nt,
+                     total, dz, domega);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E,
+                                    int N, int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
     using S = FftShape<LOGN, (int)sizeof(T)>;
-    hipLaunchKernelGGL((k_phase_to_time<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, psi, psi_jrows, A,
-                       coef, nb, j0, dz, domega, tw, ctrl);
+    hipLaunchKernelGGL((k_phase_to_time<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, psi, psi_jrows, A, E, j0,
+                       tw, ctrl);
   });
   return hipGetLastError();
 }
@@ -177,13 +185,13 @@ hipError_t Launch<T>::conv(int logn, const T* Y, T* Yout, int R, int RQ, int cou
 }
 
 template <typename T>
-hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const double* coef, int nb, int N,
-                                   int count, int j0, double dz, double domega, double gscale, double inv_omega0,
-                                   int shock, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
+hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const cplx<T>* E, int N, int count,
+                                   int j0, double domega, double gscale, double inv_omega0, int shock,
+                                   const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
     using S = FftShape<LOGN, (int)sizeof(T)>;
-    hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, coef, nb, j0,
-                       dz, domega, gscale, inv_omega0, shock, tw, ctrl);
+    hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, E, j0, domega,
+                       gscale, inv_omega0, shock, tw, ctrl);
   });
   return hipGetLastError();
 }
@@ -198,9 +206,8 @@ hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T
 }
 
 template <typename T>
-hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const double* coef, int nb, int nt, long nn, double z,
-                            double domega, hipStream_t s) {
-  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, coef, nb, nt, nn, z, domega);
+hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s) {
+  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, Em, nn);
   return hipGetLastError();
 }
 

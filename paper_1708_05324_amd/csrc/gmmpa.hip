@@ -163,6 +163,9 @@ struct gmm_plan_s {
   // workspace
   int cap = 0;  // sub-step capacity
   void *psi0 = nullptr, *I0 = nullptr, *psi = nullptr, *work = nullptr, *Bp = nullptr;
+  void* E = nullptr;    // phase table [E_rows][N][nt]: exp(D_w j dz), built per step size
+  int E_rows = 0;
+  double E_dz = 0.0;
   double* partials = nullptr;
   Ctrl* ctrl = nullptr;
   Ctrl* h_ctrl = nullptr;         // pinned
@@ -186,10 +189,11 @@ int dev_alloc(long long* counter, T** ptr, size_t bytes) {
 }
 
 void free_workspace(gmm_plan_s* P) {
-  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp, &P->Y}) {
+  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp, &P->Y, &P->E}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
+  P->E_rows = 0;
   if (P->partials) (void)hipFree(P->partials);
   P->partials = nullptr;
   P->cap = 0;
@@ -248,8 +252,9 @@ struct Runner {
     if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
     if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
     cplx<T>* W = (cplx<T>*)P->work;
-    GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, P->coef, P->nb, P->N, count, j0, dz, P->domega,
-                                     tw(), ctrl, P->stream));
+    const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
+    GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
+                                                         P->stream));
     if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
       T* Y = (T*)P->Y;
       if constexpr (std::is_same<T, float>::value) {
@@ -298,9 +303,9 @@ struct Runner {
       GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
                                                            P->N, P->Np, P->nt, count, ctrl, P->stream));
     }
-    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, P->coef, P->nb, P->N, count, j0, dz, P->domega,
-                                    P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), ctrl,
-                                    P->stream));
+    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, E, P->N, count, j0, P->domega,
+                                                           P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
+                                                           P->prm.self_steepening, tw(), ctrl, P->stream));
     return GMM_OK;
   }
 
@@ -318,8 +323,28 @@ struct Runner {
     GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
                                                    (cplx<T>*)P->I0, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl,
                                                    P->stream));
-    GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol, P->prm.fixed_iters,
-                                   P->prm.max_iter, P->stream));
+    GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol,
+                                                        P->prm.fixed_iters, P->prm.max_iter, P->stream));
+    return GMM_OK;
+  }
+
+  // Phase factors exp(D_w j dz) for j < rows (FP64 phase, rounded to the field precision).
+  int ensure_phase_table(int rows, double dz) {
+    if (P->E != nullptr && P->E_rows >= rows && P->E_dz == dz) return GMM_OK;
+    if (P->E != nullptr && P->E_rows < rows) {
+      (void)hipFree(P->E);
+      P->ws_bytes -= (long long)P->E_rows * field_bytes(P);
+      P->E = nullptr;
+      P->E_rows = 0;
+    }
+    if (P->E == nullptr) {
+      int rc = dev_alloc(&P->ws_bytes, &P->E, (size_t)rows * field_bytes(P));
+      if (rc) return rc;
+      P->E_rows = rows;
+    }
+    GMM_HIP(Launch<T>::phase_table((cplx<T>*)P->E, P->coef, P->nb, P->N, P->nt, P->E_rows, dz, P->domega,
+                                   P->stream));
+    P->E_dz = dz;
     return GMM_OK;
   }
 
@@ -350,6 +375,7 @@ struct Runner {
     const double dz = L / (double)n_small;
     int rc = ensure_workspace(P, M + 1);  // the first iteration also evaluates sub-step 0
     if (rc) return rc;
+    if ((rc = ensure_phase_table(M + 1, dz))) return rc;
     gmm_stats s{};
     s.dz_used = dz;
     // A~(0) = (1/Nt) FFT_{+}(A0)
@@ -409,8 +435,8 @@ struct Runner {
       if (c.iters > s.max_iters_seen) s.max_iters_seen = c.iters;
       s.last_eps = c.eps;
       // A~(z0 + m dz) = exp(D m dz) psi_m
-      GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0, P->coef, P->nb,
-                               P->nt, nn, m * dz, P->domega, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
+                                                   (const cplx<T>*)P->E + (size_t)m * nn, nn, P->stream));
       s.large_steps++;
       s.small_steps += m;
       done += m;
