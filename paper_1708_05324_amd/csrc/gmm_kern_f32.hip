@@ -141,11 +141,11 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
   using T = float;
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN, 4>;
+    using S = FftShape<LOGN, 4, kConvLogR<LOGN, true>>;
     const int total = (R + 1) / 2 * count;
     dim3 grid(8 * ((total + 7) / 8));
     hipLaunchKernelGGL((k_conv<float, LOGN, true>), grid, dim3(S::THREADS), 0, s, Y, nullptr, Bhi, Blo, R, RQ,
-                       count, 8, Gs, tw, ctrl);
+                       count, 32, Gs, tw, ctrl);
   });
   return hipGetLastError();
 }

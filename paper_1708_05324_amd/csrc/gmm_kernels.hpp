@@ -599,7 +599,8 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
 // vectors) and folds them into NL.  After the factor U has been staged in LDS
 // the waves never wait for each other.
 //   BF16: U and Y' as hi/lo planes; v_mfma_f32_16x16x32_bf16, products
-//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  Y' planes [count][8][Nt][8].
+//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  Y' planes of words
+//         [count][32][Nt] (word i holds rows 2i and 2i + 1).
 //   FP32: v_mfma_f32_16x16x4f32.  Y' [count][kv][Nt], rows clamped to kv - 1
 //         (U is zero there).
 __host__ __device__ constexpr int tri_mode_l(int Q) {
@@ -675,15 +676,22 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
     bf16x8 yh[BF16 ? 4 : 1][2], yl[BF16 ? 4 : 1][2];
     float yf[BF16 ? 1 : 4][BF16 ? 1 : 16];
     if constexpr (BF16) {
-      const uint4* ph = reinterpret_cast<const uint4*>(Ya) + (size_t)jj * 8 * Nt + t0 + lr;
-      const uint4* pl = reinterpret_cast<const uint4*>(Yb) + (size_t)jj * 8 * Nt + t0 + lr;
+      // word (i, t) of a plane holds rows 2i, 2i + 1: the eight rows 32 ks + 8 lk .. + 7 are words 16 ks + 4 lk + e
+      const uint32_t* ph = reinterpret_cast<const uint32_t*>(Ya) + (size_t)jj * 32 * Nt + t0 + lr;
+      const uint32_t* pl = reinterpret_cast<const uint32_t*>(Yb) + (size_t)jj * 32 * Nt + t0 + lr;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-          const size_t o = (size_t)(4 * ks + lk) * Nt + cb * 16;
-          yh[cb][ks] = __builtin_bit_cast(bf16x8, ph[o]);
-          yl[cb][ks] = __builtin_bit_cast(bf16x8, pl[o]);
+          uint32_t wh[4], wl[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const size_t o = (size_t)(16 * ks + 4 * lk + e) * Nt + cb * 16;
+            wh[e] = ph[o];
+            wl[e] = pl[o];
+          }
+          yh[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wh[0], wh[1], wh[2], wh[3]});
+          yl[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wl[0], wl[1], wl[2], wl[3]});
         }
     } else {
       const float* py = reinterpret_cast<const float*>(Ya) + (size_t)jj * kv * Nt + t0 + lr;
@@ -968,14 +976,21 @@ __global__ __launch_bounds__(256, 2) void k_project_cols(
   }
 }
 
+// Points per thread of the convolution rows: 16 for the BF16-split output up
+// to 2^14 (more waves per block, no spills), 32 otherwise.
+template <int LOGN, bool BF16OUT>
+constexpr int kConvLogR = BF16OUT && LOGN <= 14 ? 4 : 5;
+
 // k_conv: Y'_rho = g * Y_rho for rows rho < R (pairs of rows as one complex
-// transform, as in k_pairs).  Output [count][R][Nt] in T, or (BF16 split)
-// hi/lo planes [count][KB][Nt][8].  1-D grid in XCD-local order.
+// transform, as in k_pairs).  Output [count][RQ][Nt] in T, or (BF16 split)
+// hi/lo planes of 32-bit words [count][KW][Nt], word (i, t) holding rows 2i
+// (low half) and 2i + 1 (high half): each block stores whole words, so its
+// stores are contiguous.  1-D grid in XCD-local order.
 template <typename T, int LOGN, bool BF16OUT>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_conv(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF16OUT>>::THREADS)) void k_conv(
     const T* __restrict__ Y, T* __restrict__ Yout, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo, int R,
-    int RQ, int count, int KB, const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
+    int RQ, int count, int KW, const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF16OUT>>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
   const int PB = (R + 1) / 2;
@@ -996,14 +1011,14 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_c
   for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gs[tid + i * S::THREADS]);
   block_fft<S, T, -1>(z, lds, tid, tw);
   if constexpr (BF16OUT) {
-    const size_t base = (((size_t)jj * KB + (r1 >> 3)) * S::N) * 4 + ((r1 & 7) >> 1);
+    const size_t base = ((size_t)jj * KW + (r1 >> 1)) * S::N;
 #pragma unroll
     for (int i = 0; i < S::R; ++i) {
       const int t = tid + i * S::THREADS;
       uint32_t h, l;
       bf16_split2((float)z[i].re, (float)z[i].im, h, l);
-      Bhi[base + (size_t)t * 4] = h;
-      Blo[base + (size_t)t * 4] = l;
+      Bhi[base + t] = h;
+      Blo[base + t] = l;
     }
   } else {
     T* o1 = Yout + ((size_t)jj * RQ + r1) * S::N;
@@ -1018,14 +1033,20 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_c
 }
 
 // ---------------------------------------------------------------------------
+// The spectral-output transform runs 16 points per thread (twice the waves of
+// the 32-point rows per block, which measured faster for this kernel) up to
+// 2^14; a 2^15 row needs 32 points per thread to stay within 1024 threads.
+template <int LOGN>
+constexpr int kSpectralLogR = LOGN <= 14 ? 4 : 5;
+
 // a6: I_j(w) = exp(-D_w z_j) * i gamma^ (1 + s w/w0) * F{NL_j}(w),
 // F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt; exp(-D_w z_j) = conj(E[j0 + jj])
 // (E = nullptr: z = 0).  grid (N, count); in may alias out.
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_spectral_out(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out(
     const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ E, int j0, double domega, double gscale,
     double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
   if (skip_iteration(ctrl)) return;
   __shared__ T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;

@@ -175,7 +175,7 @@ template <typename T>
 hipError_t Launch<T>::conv(int logn, const T* Y, T* Yout, int R, int RQ, int count, const cplx<T>* Gs,
                            const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN, (int)sizeof(T)>;
+    using S = FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, false>>;
     const int total = (R + 1) / 2 * count;
     dim3 grid(8 * ((total + 7) / 8));
     hipLaunchKernelGGL((k_conv<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, Y, Yout, nullptr, nullptr, R, RQ,
@@ -189,7 +189,7 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
                                    int j0, double domega, double gscale, double inv_omega0, int shock,
                                    const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN, (int)sizeof(T)>;
+    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
     hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, E, j0, domega,
                        gscale, inv_omega0, shock, tw, ctrl);
   });
