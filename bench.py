@@ -40,29 +40,33 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}
 
 
 def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0) -> dict:
-    """Algorithmic work of one kernel kind for one sub-step integrand.
+    """Algorithmic work of one kernel kind for one sub-step integrand: flops
+    (of the unit named in "compute") and HBM bytes.
 
     rank > 0: the plan contracts through the factor S^ = U V (U: Np x r), so the
     Raman convolution acts on r rows and the products are 2 r Np Nt each.
     bf16x3 executes three bf16 products per useful multiply-add; the useful
-    count is what is reported (against the matching useful-work peak)."""
+    count is what is reported (against the matching useful-work peak).  The
+    sub-step transforms and the spectral output also read the phase table
+    (one complex per element)."""
     Np = N * (N + 1) // 2
-    rs = 8 if prec == "fp64" else 4
+    rs = 8 if prec == "fp64" else 4        # bytes per real (a bf16 hi/lo pair is 4 bytes too)
     cs = 2 * rs
     fft = 5.0 * Nt * math.log2(Nt)
-    rows = rank if rank else Np           # rows that are convolved
     if kind == "contract":
         k = rank if rank else Np
-        return {"bound": "mfma", "flops": 2.0 * Np * k * Nt, "bytes": k * Nt * rs + 2 * N * Nt * cs}
+        return {"compute": "mfma", "flops": 2.0 * Np * k * Nt, "bytes": k * Nt * rs + 2 * N * Nt * cs}
     if kind == "project":
-        return {"bound": "mfma", "flops": 2.0 * rank * Np * Nt, "bytes": N * Nt * cs + rank * Nt * rs}
+        return {"compute": "mfma", "flops": 2.0 * rank * Np * Nt, "bytes": N * Nt * cs + rank * Nt * rs}
     if kind == "pairs_raman":
-        return {"bound": "alu", "flops": math.ceil(rows / 2) * 2 * fft, "bytes": N * Nt * cs + rows * Nt * rs}
+        if rank:   # convolution of the r rows of Y: read Y, write Y'
+            return {"compute": "alu", "flops": math.ceil(rank / 2) * 2 * fft, "bytes": 2 * rank * Nt * rs}
+        return {"compute": "alu", "flops": math.ceil(Np / 2) * 2 * fft, "bytes": N * Nt * cs + Np * Nt * rs}
     if kind in ("phase_to_time", "spectral_out"):
-        return {"bound": "hbm", "flops": N * fft, "bytes": 2 * N * Nt * cs}
+        return {"compute": "alu", "flops": N * fft, "bytes": 3 * N * Nt * cs}
     if kind == "trapz":
-        return {"bound": "hbm", "flops": 0.0, "bytes": 3 * N * Nt * cs}
-    return {"bound": "hbm", "flops": 0.0, "bytes": 0.0}
+        return {"compute": "alu", "flops": 0.0, "bytes": 3 * N * Nt * cs}
+    return {"compute": "alu", "flops": 0.0, "bytes": 0.0}
 
 
 def read_traffic(kind: str, workload: str, prec: str):
@@ -144,34 +148,75 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     return out
 
 
+def run_rk4ip(prec: str, w, n_steps: int) -> float:
+    """Small steps/s of the serial RK4IP baseline at the workload's step."""
+    import torch
+    from paper_1708_05324_amd import gmmpa
+    plan = gmmpa.plan_from_workload(w, precision=prec)
+    A = torch.from_numpy(w.A0).to(device="cuda", dtype=torch.complex128 if prec == "fp64" else torch.complex64)
+    A = plan.propagate_rk4ip(A, 4 * w.dz, w.dz).field
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.propagate_rk4ip(A, n_steps * w.dz, w.dz)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    plan.close()
+    return res.stats["small_steps"] / sec
+
+
+def sweep_accuracy(w, n_steps: int = 40) -> dict:
+    """FP64 field error after n_steps small steps against RK4IP at dz/4: the
+    MPA (converged to 1e-12, each M) and RK4IP, both at the workload's dz."""
+    import numpy as np
+    import torch
+    from paper_1708_05324_amd import gmmpa
+    L = n_steps * w.dz
+    plan = gmmpa.plan_from_workload(w, precision="fp64", tol=1e-12, max_iter=40)
+    A0 = torch.from_numpy(w.A0).to(device="cuda", dtype=torch.complex128)
+    ref = plan.propagate_rk4ip(A0, L, w.dz / 4).field.cpu().numpy()
+    def err(x):
+        return float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+    out = {"length_small_steps": n_steps, "reference": "RK4IP at dz/4",
+           "rk4ip": err(plan.propagate_rk4ip(A0, L, w.dz).field.cpu().numpy())}
+    for M in (1, 10, 40):
+        out[f"mpa_M{M}"] = err(plan.propagate(A0, L, w.dz, M).field.cpu().numpy())
+    plan.close()
+    return out
+
+
 def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str, rank: int = 0):
-    """Roofline entry of the kernel kind with the largest total time."""
+    """Roofline entry of the kernel kind with the largest total time.  The bound
+    is the ceiling that takes longer for the kernel's algorithmic work: its
+    flops at the compute peak (MFMA, or vector ALU for the transforms) or its
+    bytes at the HBM peak; both fractions are reported."""
     kind = max(prof, key=lambda k: prof[k][0])
     total_ms, launches = prof[kind]
     evals = stats["evaluations"]          # sub-step integrands = units processed by all counted launches
     wk = work_per_eval(kind, N, Nt, prec, rank)
     sec = total_ms * 1e-3
-    if wk["bound"] == "mfma":
-        achieved = wk["flops"] * evals / sec / 1e12
-        peak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else
-                     "mfma_bf16x3_TFLOPs" if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
-        unit = "TFLOP/s"
-    elif wk["bound"] == "alu":
-        achieved = wk["flops"] * evals / sec / 1e12
-        peak = PEAKS["alu_fp64_TFLOPs" if prec == "fp64" else "alu_fp32_TFLOPs"]
-        unit = "TFLOP/s"
+    if wk["compute"] == "mfma":
+        cpeak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else
+                      "mfma_bf16x3_TFLOPs" if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
     else:
-        achieved = wk["bytes"] * evals / sec / 1e9
-        peak = PEAKS["hbm_GBps"]
-        unit = "GB/s"
+        cpeak = PEAKS["alu_fp64_TFLOPs" if prec == "fp64" else "alu_fp32_TFLOPs"]
+    t_compute = wk["flops"] / (cpeak * 1e12)
+    t_hbm = wk["bytes"] / (PEAKS["hbm_GBps"] * 1e9)
+    c_ach = wk["flops"] * evals / sec / 1e12
+    m_ach = wk["bytes"] * evals / sec / 1e9
+    if t_compute >= t_hbm:
+        bound, achieved, peak, unit = wk["compute"], c_ach, cpeak, "TFLOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", m_ach, PEAKS["hbm_GBps"], "GB/s"
     return {
         "kernel": kind,
-        "bound": wk["bound"],
+        "bound": bound,
         "achieved": round(achieved, 3),
         "peak": peak,
         "unit": unit,
         "frac": round(achieved / peak, 4),
         "traffic": read_traffic(kind, workload, prec),
+        "compute_frac": round(c_ach / cpeak, 4),
+        "hbm_frac": round(m_ach / PEAKS["hbm_GBps"], 4),
         "avg_launch_us": round(total_ms / launches * 1e3, 2) if launches else None,
         "launches": launches,
         "units_per_launch": round(evals / launches, 3) if launches else None,
@@ -206,8 +251,9 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=20)
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--sweep-M", action="store_true",
-                    help="only run the parallel-extent sweep M = 1..40 (M = 1 is the serial trapezoid) on the "
-                         "10-mode 2^14 workload with z_NL/dz = 200, and print its own JSON line")
+                    help="only run the parallel-extent sweep M = 1..40 (M = 1 is the serial trapezoid) and the "
+                         "serial RK4IP baseline on the 10-mode 2^14 workload with z_NL/dz = 200, and print its "
+                         "own JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -235,8 +281,12 @@ def main():
                                   "evaluations_per_s": round(r["evaluations_per_s"], 1)})
             print(f"M={M}: {out['points'][-1]}", file=sys.stderr, flush=True)
         base = out["points"][0]["small_steps_per_s"]
+        rk = run_rk4ip(args.precision, w, 200)
+        out["rk4ip"] = {"small_steps_per_s": round(rk, 1), "evaluations_per_step": 4}
         for pt in out["points"]:
             pt["speedup_vs_serial"] = round(pt["small_steps_per_s"] / base, 3)
+            pt["speedup_vs_rk4ip"] = round(pt["small_steps_per_s"] / rk, 3)
+        out["accuracy_fp64"] = sweep_accuracy(w)
         print(json.dumps(out), flush=True)
         return
     if args.copy_probe:

@@ -124,6 +124,17 @@ int gmm_plan_create(gmm_plan* out, const gmm_params* p, const double* betas, con
 int gmm_propagate(gmm_plan plan, const void* A0, double L, double dz, int M, void* Aout, gmm_stats* st);
 
 /*
+ * gmm_propagate_rk4ip - serial baseline of Sec. III.D: propagate A0 over L
+ * with 4th-order Runge-Kutta in the interaction picture (Hult, J. Lightwave
+ * Technol. 25, 2007), the kind of serial integrator the MPA is compared with
+ * in Fig. 3.  Each step of h evaluates the nonlinear operator four times in
+ * sequence (no sub-step parallelism).  Same plan, arguments and step rule as
+ * gmm_propagate (no M); st->evaluations = 4 n, st->iterations = 0.
+ * Returns after the result is complete.
+ */
+int gmm_propagate_rk4ip(gmm_plan plan, const void* A0, double L, double dz, void* Aout, gmm_stats* st);
+
+/*
  * gmm_nonlinear - the integrand factor of Eq. (MPA_eq) for `count` fields:
  *   out_c(w) = i (n2 w0/c) (1 + s w/w0) F{ sum_lmn [(1-fR) S_plmn A_l A_m A_n^*
  *                                            + fR S_plmn A_l (h_R * A_m A_n^*)] }

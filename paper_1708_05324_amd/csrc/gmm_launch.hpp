@@ -34,6 +34,10 @@ struct Launch {
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
   static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s);
+  // Element-wise part of one RK4IP stage (1..4) over nn elements.
+  static hipError_t rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
+                                const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,
+                                hipStream_t s);
   static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
                               hipStream_t s);
   static hipError_t finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s);

@@ -212,6 +212,15 @@ hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em,
 }
 
 template <typename T>
+hipError_t Launch<T>::rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
+                                  const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL((k_rk4ip_stage<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, stage, At, AI, k1, k2, k3, k4, X,
+                     Eh, h, nn);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
                                 hipStream_t s) {
   hipLaunchKernelGGL((k_spec_sums<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, At, nt, nn, domega, omega0,

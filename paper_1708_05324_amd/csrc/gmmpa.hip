@@ -450,6 +450,48 @@ struct Runner {
     return status;
   }
 
+  // Serial RK4IP baseline: n steps of h, four dependent evaluations each.
+  int propagate_rk4ip(const void* A0, double L, double dz_req, void* Aout, gmm_stats* st) {
+    const long nn = (long)P->N * P->nt;
+    const double r = L / dz_req;
+    long n_small = (std::fabs(r - std::round(r)) < 1e-9 * std::max(1.0, r)) ? (long)std::llround(r)
+                                                                            : (long)std::ceil(r);
+    if (n_small < 1) n_small = 1;
+    const double h = L / (double)n_small;
+    int rc = ensure_workspace(P, 6);  // AI, k1..k4, X in the sub-step rows
+    if (rc) return rc;
+    if ((rc = ensure_phase_table(2, 0.5 * h))) return rc;  // row 1: exp(D h/2)
+    gmm_stats s{};
+    s.dz_used = h;
+    cplx<T>* At = (cplx<T>*)P->psi0;
+    cplx<T>* rows = (cplx<T>*)P->psi;
+    cplx<T>*AI = rows, *k1 = rows + nn, *k2 = rows + 2 * nn, *k3 = rows + 3 * nn, *k4 = rows + 4 * nn,
+    *X = rows + 5 * nn;
+    const cplx<T>* Eh = (const cplx<T>*)P->E + nn;
+    GMM_HIP(Launch<T>::fft_rows(P->logn, +1, (const cplx<T>*)A0, At, (T)(1.0 / P->nt), P->N, tw(), P->stream));
+    if ((rc = spec_sums(At, &s.energy_in, &s.photons_in))) return rc;
+    for (long n = 0; n < n_small; ++n) {
+      if ((rc = eval(At, P->N, 1, 0, 0.0, k1, nullptr))) return rc;
+      GMM_HIP(Launch<T>::rk4ip_stage(1, At, AI, k1, k2, k3, k4, X, Eh, (T)h, nn, P->stream));
+      if ((rc = eval(X, P->N, 1, 0, 0.0, k2, nullptr))) return rc;
+      GMM_HIP(Launch<T>::rk4ip_stage(2, At, AI, k1, k2, k3, k4, X, Eh, (T)h, nn, P->stream));
+      if ((rc = eval(X, P->N, 1, 0, 0.0, k3, nullptr))) return rc;
+      GMM_HIP(Launch<T>::rk4ip_stage(3, At, AI, k1, k2, k3, k4, X, Eh, (T)h, nn, P->stream));
+      if ((rc = eval(X, P->N, 1, 0, 0.0, k4, nullptr))) return rc;
+      GMM_HIP(Launch<T>::rk4ip_stage(4, At, AI, k1, k2, k3, k4, X, Eh, (T)h, nn, P->stream));
+      P->prof.cur_step++;
+    }
+    s.large_steps = n_small;
+    s.small_steps = n_small;
+    s.evaluations = 4 * (long long)n_small;
+    if ((rc = spec_sums(At, &s.energy_out, &s.photons_out))) return rc;
+    GMM_HIP(Launch<T>::fft_rows(P->logn, -1, At, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
+    GMM_HIP(hipStreamSynchronize(P->stream));
+    if (P->prof.on) P->prof.collect();
+    if (st) *st = s;
+    return GMM_OK;
+  }
+
   int nonlinear(const void* At, int count, void* out) {
     int rc = ensure_workspace(P, count);
     if (rc) return rc;
@@ -833,6 +875,20 @@ int gmm_propagate(gmm_plan plan, const void* A0, double L, double dz, int M, voi
   try {
     int rc = plan->fp64 ? Runner<double>{plan}.propagate(A0, L, dz, M, Aout, st)
                         : Runner<float>{plan}.propagate(A0, L, dz, M, Aout, st);
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_propagate_rk4ip(gmm_plan plan, const void* A0, double L, double dz, void* Aout, gmm_stats* st) {
+  if (!plan || !A0 || !Aout) return fail(GMM_ERR_ARG, "null argument");
+  if (!(L > 0) || !(dz > 0) || !std::isfinite(L) || !std::isfinite(dz)) return fail(GMM_ERR_ARG, "L and dz must be > 0");
+  if (L / dz > 1e12) return fail(GMM_ERR_ARG, "too many small steps");
+  try {
+    int rc = plan->fp64 ? Runner<double>{plan}.propagate_rk4ip(A0, L, dz, Aout, st)
+                        : Runner<float>{plan}.propagate_rk4ip(A0, L, dz, Aout, st);
     if (rc >= 0) g_last_error.clear();
     return rc;
   } catch (...) {

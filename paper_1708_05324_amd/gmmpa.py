@@ -28,8 +28,8 @@ GMM_FP64 = 0
 GMM_FP32 = 1
 GMM_BF16X3 = 2
 
-EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_nonlinear", "gmm_plan_destroy", "gmm_last_error",
-           "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable", "gmm_profile_read")
+EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_nonlinear", "gmm_plan_destroy",
+           "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable", "gmm_profile_read")
 PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project")
 
 
@@ -69,6 +69,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_plan_create.restype = ci
     lib.gmm_propagate.argtypes = [vp, vp, dbl, dbl, ci, vp, ctypes.POINTER(gmm_stats)]
     lib.gmm_propagate.restype = ci
+    lib.gmm_propagate_rk4ip.argtypes = [vp, vp, dbl, dbl, vp, ctypes.POINTER(gmm_stats)]
+    lib.gmm_propagate_rk4ip.restype = ci
     lib.gmm_nonlinear.argtypes = [vp, vp, ci, vp]
     lib.gmm_nonlinear.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
@@ -165,6 +167,20 @@ class Plan:
         rc = self.lib.gmm_propagate(self.handle, ctypes.c_void_p(A0.data_ptr()), float(L), float(dz), int(M),
                                     ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
         _check(rc, allow=(GMM_OK, GMM_NOT_CONVERGED))
+        return Result(out, rc, st.as_dict())
+
+    def propagate_rk4ip(self, A0, L: float, dz: float, out=None) -> Result:
+        """Serial RK4IP baseline over L with steps of dz (four dependent evaluations per step)."""
+        import torch
+        self._check_field(A0)
+        if tuple(A0.shape) != (self.n_modes, self.nt):
+            raise ValueError("A0 must be [N][Nt]")
+        if out is None:
+            out = torch.empty_like(A0)
+        st = gmm_stats()
+        rc = self.lib.gmm_propagate_rk4ip(self.handle, ctypes.c_void_p(A0.data_ptr()), float(L), float(dz),
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+        _check(rc)
         return Result(out, rc, st.as_dict())
 
     def nonlinear(self, At, out=None):

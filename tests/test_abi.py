@@ -24,7 +24,7 @@ def lib():
 
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "gmmpa.h")).read()
-    return sorted(set(re.findall(r"\b(gmm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(gmm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -114,6 +114,7 @@ def test_distinct_raman_tensor_is_reported_unsupported(lib):
 
 def test_null_arguments(lib):
     assert lib.gmm_propagate(None, None, 1.0, 1.0, 1, None, None) == gmmpa.GMM_ERR_ARG
+    assert lib.gmm_propagate_rk4ip(None, None, 1.0, 1.0, None, None) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_nonlinear(None, None, 1, None) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_plan_destroy(None) == 0
     assert lib.gmm_plan_device_bytes(None) == 0

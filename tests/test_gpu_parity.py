@@ -233,3 +233,41 @@ def test_full_rank_tensor_keeps_the_packed_route(torch_gpu):
     assert plan.rank() == 0
     got = plan.nonlinear(to_dev(torch, At, "fp64")).cpu().numpy()
     assert relmax(got, ops.N(At[0])[None]) < TOL_OP["fp64"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [(2, 256, 0.0, 0, 80e-15), (3, 1024, 0.18, 1, 20e-15), (5, 1024, 0.18, 1, 20e-15)],
+                         ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}")
+def test_rk4ip_baseline_matches_oracle(torch_gpu, prec, case):
+    """The serial RK4IP baseline against the oracle's RK4IP, step for step
+    (3, 6 and 15 modes; the 15-mode plan contracts through the rank-45 factor)."""
+    torch = torch_gpu
+    g, nt, fR, s, dt = case
+    w = small_workload(N_groups=g, nt=nt, fR=fR, s=s, dt=dt)
+    m = O.model_from_workload(w)
+    L = 12 * w.dz
+    ref = O.rk4ip_propagate(w.A0, m, L, w.dz)
+    plan = make_plan(w, prec)
+    res = plan.propagate_rk4ip(to_dev(torch, w.A0, prec), L, w.dz)
+    err = relmax(res.field.cpu().numpy(), ref)
+    print(f"[{prec} {case}] rk4ip error {err:.3e} stats {res.stats}", flush=True)
+    assert err < TOL_PROP[prec]
+    assert res.stats["small_steps"] == 12 and res.stats["evaluations"] == 48
+
+
+def test_rk4ip_and_mpa_agree_to_second_order(torch_gpu):
+    """Same fibre and step: the converged MPA (2nd order) and RK4IP (4th order)
+    differ by O(dz^2); halving dz divides the difference by about 4."""
+    torch = torch_gpu
+    w = small_workload(N_groups=2, nt=512, fR=0.18, s=1, dt=40e-15)
+    L = 20 * w.dz
+    diffs = []
+    for k in (1, 2):
+        dz = w.dz / k
+        plan = make_plan(w, "fp64", tol=1e-13, max_iter=40)
+        a = plan.propagate(to_dev(torch, w.A0, "fp64"), L, dz, 5).field.cpu().numpy()
+        b = plan.propagate_rk4ip(to_dev(torch, w.A0, "fp64"), L, dz).field.cpu().numpy()
+        diffs.append(relmax(a, b))
+    ratio = diffs[0] / diffs[1]
+    print(f"MPA - RK4IP: {diffs}, ratio {ratio:.2f}", flush=True)
+    assert 3.0 < ratio < 5.0
