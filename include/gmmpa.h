@@ -65,9 +65,16 @@ typedef struct {
   double tol;           /* threshold on ||psi^(n+1) - psi^(n)|| / ||psi^(n+1)|| (FP64) */
   int max_iter;         /* iteration cap per large step (>= 1) */
   int fixed_iters;      /* > 0: run exactly this many iterations per large step, ignore tol */
-  int factor_policy;    /* 0: when the Raman term is on and the packed coupling matrix S^ has numerical
-                           rank r <= min(64, Np/2), contract through its factor S^ = U V so only r rows
-                           are convolved (same result to rounding); 1: always use S^ itself */
+  int factor_policy;    /* contraction route.  0 (auto): a real S^K = S^R with S_plmn = S_plnm = S_lpmn
+                           uses the packed matrix S^ (Np = N(N+1)/2 real rows), and, when the Raman term
+                           is on and S^ has numerical rank r <= min(64, Np/2), its factor S^ = U V so
+                           only r rows are convolved (same result to rounding); any other tensor uses
+                           the general route.  1: the packed matrix S^ itself (GMM_ERR_TENSOR if the
+                           tensor does not allow it).  2: the general route for any tensor: complex
+                           C_pl from 2 N^2 x 4 Np real coefficients (S^K != S^R, complex S, polarised
+                           modes), NL_p = sum_l C_pl A_l */
+  int s_complex;        /* 0: SK and SR hold N^4 real values; 1: N^4 complex values, interleaved
+                           (re, im) doubles */
 } gmm_params;
 
 typedef struct {
@@ -91,12 +98,13 @@ typedef struct {
  *   betas  : host [N][n_beta] Taylor coefficients about omega0 (rad/m, s/m,
  *            s^2/m, ...); columns 0 and 1 relative to the first mode
  *            (paragraph after Eq. (1)).  Copied.
- *   SK     : host [N^4] real coupling tensor S^K_plmn, index ((p*N+l)*N+m)*N+n,
- *            in m^-2 (Eq. (2)).  It must satisfy S_plmn = S_plnm = S_lpmn
- *            (true for Eq. (2)); otherwise GMM_ERR_TENSOR.  Copied.
- *   SR     : host [N^4] Raman tensor, or NULL for S^R = S^K (Eq. (2) with real
- *            scalar modes).  A non-NULL SR different from SK returns
- *            GMM_ERR_UNSUPPORTED in this build.
+ *   SK     : host [N^4] coupling tensor S^K_plmn of Eq. (1), index
+ *            ((p*N+l)*N+m)*N+n, in m^-2 (Eq. (2) for real scalar modes); real,
+ *            or complex when p->s_complex = 1 ([N^4][2] doubles).  Any tensor is
+ *            accepted; factor_policy says which contraction route it takes.
+ *            Copied.
+ *   SR     : host Raman tensor S^R_plmn in the same layout, or NULL for
+ *            S^R = S^K (Eq. (2) with real scalar modes).  Copied.
  *   hR     : host [Nt] samples h_R(k dt), k = 0..Nt-1 (1/s); required when
  *            fR > 0, ignored otherwise.  Copied.
  *   stream : hipStream_t on which all work of this plan is queued (NULL =

@@ -1033,6 +1033,124 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF1
 }
 
 // ---------------------------------------------------------------------------
+// General-tensor route (S^K != S^R, complex S, or S without the (m, n) and
+// (p, l) symmetries, e.g. polarised modes).  With B_mn = A_m A_n^* Hermitian in
+// (m, n) and h_R real, each unordered pair Q = (m <= n) carries four real rows
+//   x_Q = Re B_mn,  y_Q = Im B_mn,  xr_Q = Re (h_R * B_mn),  yr_Q = Im (h_R * B_mn)
+// and C_pl = sum_Q [(K_plmn + K_plnm) x + i (K_plmn - K_plnm) y
+//                   + (R_plmn + R_plnm) xr + i (R_plmn - R_plnm) yr]
+// (K = (1 - fR) S^K, R = fR S^R; the diagonal pairs count once), a real GEMM
+// with 2 N^2 output rows (Re C_pl, Im C_pl) and K = 4 Np (2 Np without Raman).
+//
+// k_pairs_dense: one block per (pair, sub-step), XCD-local 1-D grid: the
+// complex product row B_mn and, with Raman, its convolution with h_R (one
+// complex transform pair; Hr = H / (H0 Nt)).  Output [count][KD][Nt] rows
+// Q, Np + Q, 2 Np + Q, 3 Np + Q.
+template <typename T, int LOGN, bool RAMAN>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_pairs_dense(
+    const cplx<T>* __restrict__ A, T* __restrict__ Bd, const int2* __restrict__ pairs, int N, int Np, int count,
+    int KD, const cplx<T>* __restrict__ Hr, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T)>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, Np * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x, jj = w / Np, Q = w - jj * Np;
+  const int2 mn = pairs[Q];
+  const cplx<T>* am = A + ((size_t)jj * N + mn.x) * S::N;
+  const cplx<T>* an = A + ((size_t)jj * N + mn.y) * S::N;
+  T* out = Bd + (size_t)jj * KD * S::N;
+  cplx<T> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = tid + i * S::THREADS;
+    const cplx<T> x = am[t], y = an[t];
+    z[i] = {x.re * y.re + x.im * y.im, x.im * y.re - x.re * y.im};  // A_m conj(A_n)
+    out[(size_t)Q * S::N + t] = z[i].re;
+    out[(size_t)(Np + Q) * S::N + t] = z[i].im;
+  }
+  if constexpr (RAMAN) {
+    block_fft<S, T, +1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Hr[tid + i * S::THREADS]);
+    block_fft<S, T, -1>(z, lds, tid, tw);
+#pragma unroll
+    for (int i = 0; i < S::R; ++i) {
+      const int t = tid + i * S::THREADS;
+      out[(size_t)(2 * Np + Q) * S::N + t] = z[i].re;
+      out[(size_t)(3 * Np + Q) * S::N + t] = z[i].im;
+    }
+  }
+}
+
+// k_contract_dense: C = G B on MFMA for one 64-column tile per block, 64 output
+// rows at a time (wave w: rows 16 w .. 16 w + 15 of the chunk), G [rows_pad][KD]
+// and the B tile read from L2/HBM; each chunk of C goes through LDS and is folded
+// into NL_p(t) = sum_l C_pl(t) A_l(t) (complex), thread (t, g) owning the modes
+// p = g mod 4.  Rows are 2 (p N + l) + {0: Re, 1: Im}; KD is a multiple of 4 and
+// the rows of G and B beyond the real ones are zero.  NL overwrites A.
+template <typename T>
+constexpr size_t contract_dense_lds(int nmax) {
+  return (size_t)64 * 64 * sizeof(T) + (size_t)2 * nmax * 64 * sizeof(cplx<T>);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_contract_dense(const T* __restrict__ G, const T* __restrict__ Bd,
+                                                        cplx<T>* A_NL, int N, int KD, int rows_pad, int Nt,
+                                                        const Ctrl* ctrl) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sC = reinterpret_cast<T*>(smem_raw);                      // [64][64]
+  cplx<T>* sA = reinterpret_cast<cplx<T>*>(sC + 64 * 64);       // [N][64]
+  cplx<T>* sNL = sA + N * 64;                                   // [N][64]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tiles_per_j = Nt / 64;
+  const int jj = blockIdx.x / tiles_per_j, t0 = (blockIdx.x - jj * tiles_per_j) * 64;
+  cplx<T>* Aj = A_NL + (size_t)jj * N * Nt + t0;
+  const T* Bj = Bd + (size_t)jj * KD * Nt + t0 + lr;
+  for (int i = tid; i < N * 64; i += 256) {
+    sA[i] = Aj[(size_t)(i >> 6) * Nt + (i & 63)];
+    sNL[i] = cplx<T>{T(0), T(0)};
+  }
+  const int NN = N * N;
+  for (int c0 = 0; c0 < rows_pad; c0 += 64) {
+    acc_t acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+    const T* grow = G + (size_t)(c0 + 16 * wave + lr) * KD + lk;
+    for (int k = 0; k < KD; k += 4) {
+      const T a = grow[k];
+      const T* brow = Bj + (size_t)(k + lk) * Nt;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = Mfma<T>::mma(a, brow[cb * 16], acc[cb]);
+    }
+    __syncthreads();  // the previous chunk's fold has finished reading sC
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sC[(16 * wave + Mfma<T>::out_row(lk, i)) * 64 + cb * 16 + lr] = acc[cb][i];
+    __syncthreads();
+    const int g = tid >> 6;
+    for (int r2 = 0; r2 < 32; ++r2) {
+      const int pl = (c0 >> 1) + r2;
+      if (pl >= NN) break;
+      const int p = pl / N, l = pl - p * N;
+      if ((p & 3) != g) continue;
+      const T cr = sC[(2 * r2) * 64 + lane], ci = sC[(2 * r2 + 1) * 64 + lane];
+      const cplx<T> a = sA[l * 64 + lane];
+      cplx<T>& o = sNL[p * 64 + lane];
+      o.re += cr * a.re - ci * a.im;
+      o.im += cr * a.im + ci * a.re;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < N * 64; i += 256) Aj[(size_t)(i >> 6) * Nt + (i & 63)] = sNL[i];
+}
+
+// ---------------------------------------------------------------------------
 // The spectral-output transform runs 16 points per thread (twice the waves of
 // the 32-point rows per block, which measured faster for this kernel) up to
 // 2^14; a 2^15 row needs 32 points per thread to stay within 1024 threads.

@@ -34,6 +34,12 @@ struct Launch {
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
   static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s);
+  // General-tensor route: pair rows [count][KD][Nt] (x, y and, with Raman, xr, yr), then C = G B and NL.
+  static hipError_t pairs_dense(int logn, bool raman, const cplx<T>* A, T* Bd, const int2* pairs, int N, int Np,
+                                int count, int KD, const cplx<T>* Hr, const cplx<T>* tw, const Ctrl* ctrl,
+                                hipStream_t s);
+  static hipError_t contract_dense(const T* G, const T* Bd, cplx<T>* A_NL, int N, int KD, int rows_pad, int Nt,
+                                   int count, const Ctrl* ctrl, hipStream_t s);
   // Element-wise part of one RK4IP stage (1..4) over nn elements.
   static hipError_t rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
                                 const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,

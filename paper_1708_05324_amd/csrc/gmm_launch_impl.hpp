@@ -212,6 +212,39 @@ hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em,
 }
 
 template <typename T>
+hipError_t Launch<T>::pairs_dense(int logn, bool raman, const cplx<T>* A, T* Bd, const int2* pairs, int N, int Np,
+                                  int count, int KD, const cplx<T>* Hr, const cplx<T>* tw, const Ctrl* ctrl,
+                                  hipStream_t s) {
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, (int)sizeof(T)>;
+    const int total = Np * count;
+    dim3 grid(8 * ((total + 7) / 8));
+    if (raman)
+      hipLaunchKernelGGL((k_pairs_dense<T, LOGN, true>), grid, dim3(S::THREADS), 0, s, A, Bd, pairs, N, Np, count,
+                         KD, Hr, tw, ctrl);
+    else
+      hipLaunchKernelGGL((k_pairs_dense<T, LOGN, false>), grid, dim3(S::THREADS), 0, s, A, Bd, pairs, N, Np, count,
+                         KD, Hr, tw, ctrl);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::contract_dense(const T* G, const T* Bd, cplx<T>* A_NL, int N, int KD, int rows_pad, int Nt,
+                                     int count, const Ctrl* ctrl, hipStream_t s) {
+  const size_t lds = (size_t)64 * 64 * sizeof(T) + (size_t)2 * N * 64 * sizeof(cplx<T>);
+  if (lds > 65536) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_contract_dense<T>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)contract_dense_lds<T>(22));
+    if (attr != hipSuccess) return attr;
+  }
+  hipLaunchKernelGGL((k_contract_dense<T>), dim3(count * (Nt / 64)), dim3(256), lds, s, G, Bd, A_NL, N, KD,
+                     rows_pad, Nt, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
                                   const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,
                                   hipStream_t s) {

@@ -158,6 +158,10 @@ struct gmm_plan_s {
   void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
   void* Vlo = nullptr;
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
+  // general-tensor route (S^R != S^K, complex S, or S without the packed symmetries)
+  bool dense = false;
+  int KD = 0, rows_pad = 0;  // real pair rows per sub-step (multiple of 4); output rows 2 N^2 padded to 64
+  void* G = nullptr;         // [rows_pad][KD] real coupling matrix of the general route, field precision
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
   // workspace
@@ -204,6 +208,7 @@ size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->e
 
 // B' for `cap` sub-steps: [cap][Np][Nt] reals, or two bf16 planes [cap][Kpad/8][Nt][8].
 size_t bp_bytes(const gmm_plan_s* P, int cap) {
+  if (P->dense) return (size_t)cap * P->KD * P->nt * P->esz;
   if (P->bf16) return 2 * (size_t)cap * gmm::kBf16Kpad * P->nt * 2;
   // packed route: [cap][Np][Nt]; rank-r route: Y' [cap][RQ][Nt] (RQ can exceed Np for small Np)
   const int rows = P->factored ? std::max(P->Np, P->rq) : P->Np;
@@ -227,7 +232,7 @@ int ensure_workspace(gmm_plan_s* P, int cap) {
   }
   // BF16 pair slots beyond Np, and rows R..RQ-1 of the rank-r route, are read
   // by the contraction (with zero coefficients) but never written: keep them 0.
-  if (P->bf16 || P->factored) {
+  if (P->bf16 || P->factored || P->dense) {
     if (hipMemset(P->Bp, 0, bp_bytes(P, cap)) != hipSuccess) {
       free_workspace(P);
       return fail(GMM_ERR_HIP, "hipMemset of the pair buffer failed");
@@ -255,7 +260,13 @@ struct Runner {
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
                                                          P->stream));
-    if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
+    if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
+      GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
+                                                           count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
+                                                           P->stream));
+      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)P->Bp, W, P->N, P->KD,
+                                                                 P->rows_pad, P->nt, count, ctrl, P->stream));
+    } else if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
       T* Y = (T*)P->Y;
       if constexpr (std::is_same<T, float>::value) {
         GMM_LAUNCH(P, GMM_PROF_PROJECT,
@@ -288,7 +299,7 @@ struct Runner {
         }
       }
     } else if constexpr (std::is_same<T, float>::value) {
-      if (P->bf16) {
+      if (P->bf16) {  // packed route, BF16 split
         uint32_t* bhi = (uint32_t*)P->Bp;
         uint32_t* blo = bhi + bp_plane_words(P);
         GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
@@ -297,7 +308,7 @@ struct Runner {
                                                                    P->N, P->nt, count, ctrl, P->stream));
       }
     }
-    if (!P->bf16 && !P->factored) {
+    if (!P->bf16 && !P->factored && !P->dense) {
       GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
       GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
@@ -683,9 +694,54 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
   return GMM_OK;
 }
 
+// Real coupling matrix of the general route, G [rows_pad][KD]: output rows
+// 2 (p N + l) + {0: Re C_pl, 1: Im C_pl}; columns Q (x), Np + Q (y), and with
+// Raman 2 Np + Q (xr), 3 Np + Q (yr), for the pairs Q = (m <= n):
+//   C_pl += (K_plmn + K_plnm) x + i (K_plmn - K_plnm) y   (m < n),  K_plmm x  (m = n)
+// with K = (1 - fR) S^K, and the same with R = fR S^R on (xr, yr).
+template <typename T, typename FK, typename FR>
+int upload_dense(gmm_plan_s* P, FK sk, FR sr) {
+  const int N = P->N, Np = P->Np;
+  const double fR = P->prm.fR;
+  const int kreal = (P->raman ? 4 : 2) * Np;
+  P->KD = (kreal + 3) / 4 * 4;
+  P->rows_pad = (2 * N * N + 63) / 64 * 64;
+  std::vector<T> g((size_t)P->rows_pad * P->KD, T(0));
+  auto at = [&](int p, int l, int m, int n) { return (((size_t)p * N + l) * N + m) * N + n; };
+  for (int p = 0; p < N; ++p)
+    for (int l = 0; l < N; ++l) {
+      const size_t ore = (size_t)2 * (p * N + l) * P->KD, oim = ore + P->KD;
+      for (int Q = 0; Q < Np; ++Q) {
+        int m = 0, n = 0;
+        while ((n + 1) * (n + 2) / 2 <= Q) ++n;
+        m = Q - n * (n + 1) / 2;
+        for (int part = 0; part < (P->raman ? 2 : 1); ++part) {
+          const double f = part == 0 ? 1.0 - fR : fR;
+          const std::complex<double> a = f * (part == 0 ? sk(at(p, l, m, n)) : sr(at(p, l, m, n)));
+          const std::complex<double> b = f * (part == 0 ? sk(at(p, l, n, m)) : sr(at(p, l, n, m)));
+          const int cx = 2 * part * Np + Q, cy = cx + Np;
+          if (m == n) {
+            g[ore + cx] = (T)a.real();
+            g[oim + cx] = (T)a.imag();
+          } else {
+            const std::complex<double> sum = a + b, dif = a - b;
+            g[ore + cx] = (T)sum.real();
+            g[oim + cx] = (T)sum.imag();
+            g[ore + cy] = (T)(-dif.imag());
+            g[oim + cy] = (T)dif.real();
+          }
+        }
+      }
+    }
+  int rc;
+  if ((rc = dev_alloc(&P->const_bytes, &P->G, g.size() * sizeof(T)))) return rc;
+  GMM_HIP(hipMemcpy(P->G, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GMM_OK;
+}
+
 template <typename T>
-int build_raman(gmm_plan_s* P, const double* hR) {
-  // weights h_R(k dt) normalised to unit sum; H = FFT_{+}(w); Hs = H / H[0] / Nt
+int build_raman(gmm_plan_s* P, const double* hR, double blend) {
+  // weights h_R(k dt) normalised to unit sum; H = FFT_{+}(w); Hs = ((1 - blend) + blend H / H[0]) / Nt
   const int n = P->nt;
   double sum = 0.0;
   for (int k = 0; k < n; ++k) sum += hR[k];
@@ -700,7 +756,7 @@ int build_raman(gmm_plan_s* P, const double* hR) {
   for (int k = 0; k < n; ++k) h[k] = cplx<double>{a[k].real(), a[k].imag()};
   GMM_HIP(hipMemcpy(dH, h.data(), n * sizeof(cplx<double>), hipMemcpyHostToDevice));
   if ((rc = dev_alloc(&P->const_bytes, (cplx<T>**)&P->Hs, n * sizeof(cplx<T>)))) return rc;
-  GMM_HIP(Launch<T>::finish_H(dH, (cplx<T>*)P->Hs, n, P->prm.fR, P->stream));
+  GMM_HIP(Launch<T>::finish_H(dH, (cplx<T>*)P->Hs, n, blend, P->stream));
   GMM_HIP(hipStreamSynchronize(P->stream));
   (void)hipFree(dH);
   P->const_bytes -= (long long)(n * sizeof(cplx<double>));
@@ -711,7 +767,7 @@ void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
-                  (void*)P->pidx,
+                  P->G, (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
@@ -738,7 +794,8 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (!(p->dt > 0) || !(p->omega0 > 0) || !(p->n2 >= 0) || !(p->fR >= 0 && p->fR <= 1))
     return fail(GMM_ERR_ARG, "dt, omega0 must be > 0; n2 >= 0; 0 <= fR <= 1");
   if (p->max_iter < 1 || p->fixed_iters < 0 || !(p->tol >= 0)) return fail(GMM_ERR_ARG, "bad iteration control");
-  if (p->factor_policy != 0 && p->factor_policy != 1) return fail(GMM_ERR_ARG, "factor_policy must be 0 or 1");
+  if (p->factor_policy < 0 || p->factor_policy > 2) return fail(GMM_ERR_ARG, "factor_policy must be 0, 1 or 2");
+  if (p->s_complex != 0 && p->s_complex != 1) return fail(GMM_ERR_ARG, "s_complex must be 0 or 1");
   const double domega = 2.0 * kPi / (nt * p->dt);
   if (p->self_steepening && !(p->omega0 - domega * (nt / 2) > 0))
     return fail(GMM_ERR_ARG, "1 + omega/omega0 <= 0 on the grid: window too fine for the shock term");
@@ -747,31 +804,51 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   const int Np = N * (N + 1) / 2;
   const int rpad = ((Np + 63) / 64) * 64;
   if (rpad > gmm::contract_max_rows())
-    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: packed contraction exceeds 256 rows in this build");
+    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: the contraction exceeds 256 pair rows in this build");
   if (bf16 && Np > gmm::kBf16Kpad)
     return fail(GMM_ERR_UNSUPPORTED, "the BF16 split contraction supports up to 15 modes in this build");
-  // tensor checks: real, S_plmn = S_plnm = S_lpmn
+  // tensors: real [N^4] or complex [N^4][2] (s_complex); S^R = S^K when SR is NULL
   const size_t n4 = (size_t)N * N * N * N;
+  const bool cplxS = p->s_complex == 1;
+  auto sk = [&](size_t i) { return cplxS ? std::complex<double>(SK[2 * i], SK[2 * i + 1]) : std::complex<double>(SK[i], 0.0); };
+  auto sr = [&](size_t i) {
+    if (!SR) return sk(i);
+    return cplxS ? std::complex<double>(SR[2 * i], SR[2 * i + 1]) : std::complex<double>(SR[i], 0.0);
+  };
   double smax = 0;
+  bool has_imag = false;
   for (size_t i = 0; i < n4; ++i) {
-    if (!std::isfinite(SK[i])) return fail(GMM_ERR_ARG, "non-finite S^K");
-    smax = std::max(smax, std::fabs(SK[i]));
+    const std::complex<double> a = sk(i), b = sr(i);
+    if (!std::isfinite(a.real()) || !std::isfinite(a.imag()) || !std::isfinite(b.real()) || !std::isfinite(b.imag()))
+      return fail(GMM_ERR_ARG, "non-finite S^K or S^R");
+    smax = std::max(smax, std::max(std::abs(a), std::abs(b)));
+    has_imag = has_imag || a.imag() != 0.0 || b.imag() != 0.0;
   }
-  auto S4 = [&](int a, int b, int c, int d) { return SK[(((size_t)a * N + b) * N + c) * N + d]; };
   const double stol = 1e-12 * smax;
-  for (int a = 0; a < N; ++a)
-    for (int b = 0; b < N; ++b)
-      for (int c = 0; c < N; ++c)
+  auto idx4 = [&](int a, int b, int c, int d) { return (((size_t)a * N + b) * N + c) * N + d; };
+  // the packed and rank-r routes need a real S^K = S^R with S_plmn = S_plnm = S_lpmn
+  bool packable = !has_imag;
+  for (size_t i = 0; packable && i < n4; ++i)
+    if (std::abs(sk(i) - sr(i)) > stol) packable = false;
+  for (int a = 0; packable && a < N; ++a)
+    for (int b = 0; packable && b < N; ++b)
+      for (int c = 0; packable && c < N; ++c)
         for (int d = 0; d < N; ++d) {
-          const double v = S4(a, b, c, d);
-          if (std::fabs(v - S4(a, b, d, c)) > stol || std::fabs(v - S4(b, a, c, d)) > stol)
-            return fail(GMM_ERR_TENSOR, "S^K must satisfy S_plmn = S_plnm = S_lpmn for the packed contraction");
+          const double v = sk(idx4(a, b, c, d)).real();
+          if (std::fabs(v - sk(idx4(a, b, d, c)).real()) > stol || std::fabs(v - sk(idx4(b, a, c, d)).real()) > stol) {
+            packable = false;
+            break;
+          }
         }
-  if (SR) {
-    for (size_t i = 0; i < n4; ++i)
-      if (std::fabs(SR[i] - SK[i]) > stol)
-        return fail(GMM_ERR_UNSUPPORTED, "S^R different from S^K is not implemented in this build");
+  if (p->factor_policy == 1 && !packable)
+    return fail(GMM_ERR_TENSOR, "the packed contraction needs a real S^K = S^R with S_plmn = S_plnm = S_lpmn");
+  const bool dense = p->factor_policy == 2 || !packable;
+  std::vector<double> skr;  // real S^K for the packed routes
+  if (!dense) {
+    skr.resize(n4);
+    for (size_t i = 0; i < n4; ++i) skr[i] = sk(i).real();
   }
+  auto S4 = [&](int a, int b, int c, int d) { return skr[idx4(a, b, c, d)]; };
 
   gmm_plan_s* P = new gmm_plan_s();
   P->prm = *p;
@@ -789,6 +866,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   P->bf16 = bf16;
   P->raman = raman;
   P->esz = fp64 ? 8 : 4;
+  P->dense = dense;
 
   int rc = GMM_OK;
   auto bail = [&](int code) {
@@ -819,12 +897,13 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     }
   // packed coupling matrix  S^_{(p,l),(m,n)} = w_mn S_plmn, w = 1 (m = n) or 2; stored transposed
   std::vector<double> ST((size_t)rpad * rpad, 0.0);
-  for (int r = 0; r < Np; ++r)
-    for (int q = 0; q < Np; ++q) {
-      const int2 pl = pairs[r], mn = pairs[q];
-      const double w = mn.x == mn.y ? 1.0 : 2.0;
-      ST[(size_t)q * rpad + r] = w * S4(pl.x, pl.y, mn.x, mn.y);
-    }
+  if (!dense)
+    for (int r = 0; r < Np; ++r)
+      for (int q = 0; q < Np; ++q) {
+        const int2 pl = pairs[r], mn = pairs[q];
+        const double w = mn.x == mn.y ? 1.0 : 2.0;
+        ST[(size_t)q * rpad + r] = w * S4(pl.x, pl.y, mn.x, mn.y);
+      }
   // twiddles exp(-2 pi i m / nt)
   std::vector<std::complex<double>> tw(nt);
   for (int m = 0; m < nt; ++m) tw[m] = std::polar(1.0, -2.0 * kPi * (double)m / nt);
@@ -835,12 +914,18 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     return bail(fail(GMM_ERR_HIP, "copy of pair tables failed"));
   rc = fp64 ? upload_typed<double>(P, ST, tw) : upload_typed<float>(P, ST, tw);
   if (rc) return bail(rc);
-  if (bf16 && (rc = upload_bf16_split(P, ST))) return bail(rc);
-  if (raman) {
-    rc = fp64 ? build_raman<double>(P, hR) : build_raman<float>(P, hR);
+  if (dense) {
+    rc = fp64 ? upload_dense<double>(P, sk, sr) : upload_dense<float>(P, sk, sr);
     if (rc) return bail(rc);
-    if (p->factor_policy == 0) {
-      rc = fp64 ? try_factor<double>(P, SK, pairs, ST) : try_factor<float>(P, SK, pairs, ST);
+  } else if (bf16 && (rc = upload_bf16_split(P, ST))) {
+    return bail(rc);
+  }
+  if (raman) {  // the general route convolves with H itself; the packed routes with the blend (1 - fR) + fR H
+    const double blend = dense ? 1.0 : p->fR;
+    rc = fp64 ? build_raman<double>(P, hR, blend) : build_raman<float>(P, hR, blend);
+    if (rc) return bail(rc);
+    if (!dense && p->factor_policy == 0) {
+      rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
     }
   }

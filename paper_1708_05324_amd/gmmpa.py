@@ -38,7 +38,7 @@ class gmm_params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("omega0", ctypes.c_double), ("n2", ctypes.c_double),
                 ("fR", ctypes.c_double), ("self_steepening", ctypes.c_int), ("precision", ctypes.c_int),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("factor_policy", ctypes.c_int)]
+                ("factor_policy", ctypes.c_int), ("s_complex", ctypes.c_int)]
 
 
 class gmm_stats(ctypes.Structure):
@@ -117,6 +117,8 @@ class Plan:
 
     precision: "fp64" (complex128 fields), "fp32" (complex64 fields) or "bf16x3"
     (complex64 fields, BF16 hi/lo split contraction with FP32 accumulation).
+    SK, SR: real or complex [N]*4 tensors (SR None: S^R = S^K); factor_policy
+    0/1/2 picks the contraction route as documented in include/gmmpa.h.
     """
 
     def __init__(self, betas, SK, hR=None, *, nt: int, dt: float, omega0: float, n2: float, fR: float,
@@ -125,11 +127,15 @@ class Plan:
         import torch
         self.lib = load_library()
         betas = np.ascontiguousarray(np.atleast_2d(np.asarray(betas, dtype=np.float64)))
-        SK = np.ascontiguousarray(np.asarray(SK, dtype=np.float64))
         self.n_modes = betas.shape[0]
+        s_complex = int(np.iscomplexobj(SK) or (SR is not None and np.iscomplexobj(SR)))
+        sdt = np.complex128 if s_complex else np.float64
+        SK = np.ascontiguousarray(np.asarray(SK, dtype=sdt))
         if SK.size != self.n_modes ** 4:
             raise ValueError("SK must hold N^4 values")
-        SR = None if SR is None else np.ascontiguousarray(np.asarray(SR, dtype=np.float64))
+        SR = None if SR is None else np.ascontiguousarray(np.asarray(SR, dtype=sdt))
+        if SR is not None and SR.size != self.n_modes ** 4:
+            raise ValueError("SR must hold N^4 values")
         hR = None if hR is None else np.ascontiguousarray(np.asarray(hR, dtype=np.float64))
         if hR is not None and hR.size != nt:
             raise ValueError("hR must hold nt samples")
@@ -138,7 +144,7 @@ class Plan:
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
         prec = {"fp64": GMM_FP64, "fp32": GMM_FP32, "bf16x3": GMM_BF16X3}[precision]
         self.params = gmm_params(self.n_modes, nt, betas.shape[1], dt, omega0, n2, fR, int(self_steepening),
-                                 prec, tol, max_iter, fixed_iters, factor_policy)
+                                 prec, tol, max_iter, fixed_iters, factor_policy, s_complex)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -289,3 +289,14 @@ def random_symmetric_tensor(seed: int, n_modes: int) -> np.ndarray:
     for perm in itertools.permutations(range(4)):
         S += np.transpose(X, perm)
     return S / 24.0
+
+
+def random_general_tensor(seed: int, n_modes: int, complex_values: bool = True) -> np.ndarray:
+    """A random tensor without any index symmetry (real or complex, entries of
+    order one): the kind of S^K or S^R that polarised or complex modes give,
+    for testing the general contraction route."""
+    rng = np.random.default_rng(SEED_BASE + 3000 + seed)
+    S = rng.standard_normal((n_modes,) * 4)
+    if complex_values:
+        S = S + 1j * rng.standard_normal((n_modes,) * 4)
+    return S

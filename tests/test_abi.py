@@ -59,7 +59,8 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 def _params(**kw):
     base = dict(n_modes=3, nt=256, n_beta=3, dt=10e-15, omega0=synth.GrinFiber().omega0, n2=2.3e-20,
-                fR=0.0, self_steepening=0, precision=0, tol=1e-12, max_iter=20, fixed_iters=0, factor_policy=0)
+                fR=0.0, self_steepening=0, precision=0, tol=1e-12, max_iter=20, fixed_iters=0, factor_policy=0,
+                s_complex=0)
     base.update(kw)
     return gmmpa.gmm_params(**base)
 
@@ -86,7 +87,8 @@ def _create(lib, prm, S=None, hR=None, SR=None, betas=None):
     (dict(dt=0.0), gmmpa.GMM_ERR_ARG),
     (dict(fR=1.5), gmmpa.GMM_ERR_ARG),
     (dict(max_iter=0), gmmpa.GMM_ERR_ARG),
-    (dict(factor_policy=2), gmmpa.GMM_ERR_ARG),
+    (dict(factor_policy=3), gmmpa.GMM_ERR_ARG),
+    (dict(s_complex=2), gmmpa.GMM_ERR_ARG),
     (dict(fR=0.18), gmmpa.GMM_ERR_ARG),                     # Raman without h_R
     (dict(self_steepening=1, dt=0.5e-15), gmmpa.GMM_ERR_ARG),   # 1 + w/w0 <= 0 on the grid
     (dict(n_modes=23, nt=256), gmmpa.GMM_ERR_UNSUPPORTED),  # beyond 256 packed rows
@@ -99,17 +101,16 @@ def test_invalid_plans_are_rejected(lib, kw, code):
     assert lib.gmm_last_error().decode() != ""
 
 
-def test_asymmetric_tensor_is_rejected(lib):
+def test_packed_route_rejects_tensors_without_its_symmetries(lib):
+    """factor_policy 1 insists on the packed matrix: a tensor without
+    S_plmn = S_plnm, or with S^R != S^K, is reported (no GPU work involved)."""
     S = synth.random_symmetric_tensor(1, 3)
     S[0, 1, 2, 0] += 1.0                                     # breaks S_plmn = S_plnm
-    rc, _ = _create(lib, _params(), S=S)
+    rc, _ = _create(lib, _params(factor_policy=1), S=S)
     assert rc == gmmpa.GMM_ERR_TENSOR
-
-
-def test_distinct_raman_tensor_is_reported_unsupported(lib):
     S = synth.random_symmetric_tensor(1, 3)
-    rc, _ = _create(lib, _params(), S=S, SR=2.0 * S)
-    assert rc == gmmpa.GMM_ERR_UNSUPPORTED
+    rc, _ = _create(lib, _params(factor_policy=1), S=S, SR=2.0 * S)
+    assert rc == gmmpa.GMM_ERR_TENSOR
 
 
 def test_null_arguments(lib):

@@ -271,3 +271,83 @@ def test_rk4ip_and_mpa_agree_to_second_order(torch_gpu):
     ratio = diffs[0] / diffs[1]
     print(f"MPA - RK4IP: {diffs}, ratio {ratio:.2f}", flush=True)
     assert 3.0 < ratio < 5.0
+
+
+def _general_model(w, complex_values, distinct_raman, seed=0):
+    """The workload's fibre with a general coupling tensor (no index symmetry),
+    scaled like its Eq. (2) tensor; S^R differs from S^K when asked."""
+    scale = float(w.S[0, 0, 0, 0])
+    SK = synth.random_general_tensor(seed, w.n_modes, complex_values) * scale
+    SR = synth.random_general_tensor(seed + 1, w.n_modes, complex_values) * scale if distinct_raman else None
+    m = O.Model(betas=np.asarray(w.betas, float), SK=SK, SR=SR, fR=float(w.fR),
+                hR=None if w.hR is None else np.asarray(w.hR, float), dt=float(w.dt), omega0=float(w.omega0),
+                n2=float(w.n2), self_steepening=int(w.self_steepening))
+    return m, SK, SR
+
+
+def _general_plan(w, SK, SR, prec, **kw):
+    from paper_1708_05324_amd import gmmpa
+    return gmmpa.Plan(w.betas, SK, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,
+                      self_steepening=w.self_steepening, precision=prec, SR=SR, **kw)
+
+
+GENERAL_CASES = [  # (groups, nt, fR, complex S, distinct S^R)
+    (1, 256, 0.0, True, False),      # one mode, complex S
+    (2, 256, 0.0, True, False),      # 3 modes, Kerr only, complex non-symmetric S
+    (2, 512, 0.18, False, True),     # 3 modes, real S without the (m, n) symmetry, S^R != S^K
+    (3, 1024, 0.18, True, True),     # 6 modes, complex S^K != S^R, Raman + shock
+    (5, 256, 0.18, True, True),      # 15 modes: 450 output rows, K = 480
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", GENERAL_CASES, ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_c{int(c[3])}_r{int(c[4])}")
+def test_general_route_operator_matches_oracle(torch_gpu, prec, case):
+    """General-tensor route (complex S, S^R != S^K, no index symmetry) against
+    the oracle's dense evaluation of the bracket of Eq. (1)."""
+    torch = torch_gpu
+    g, nt, fR, cplx, distinct = case
+    w = small_workload(N_groups=g, nt=nt, fR=fR, s=1, dt=20480e-15 / nt)
+    m, SK, SR = _general_model(w, cplx, distinct)
+    ops = O._Ops(m, w.nt)
+    spectra = [O.to_spectrum(w.A0 + 0.3 * c * synth.random_fields(c, w.n_modes, w.nt, scale=100.0))
+               for c in range(2)]
+    ref = np.stack([ops.N(a) for a in spectra])
+    plan = _general_plan(w, SK, SR, prec)
+    got = plan.nonlinear(to_dev(torch, np.stack(spectra), prec)).cpu().numpy()
+    err = relmax(got, ref)
+    print(f"[{prec} {case}] general route operator error {err:.3e}", flush=True)
+    assert err < {"fp64": 1e-11, "fp32": 2e-5, "bf16x3": 2e-5}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_general_route_equals_packed_route_on_eq2_tensors(torch_gpu, prec):
+    """An Eq. (2) tensor through the general route (factor_policy 2) gives the
+    packed route's result (factor_policy 1) and the oracle's."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    m = O.model_from_workload(w)
+    ops = O._Ops(m, w.nt)
+    At = O.to_spectrum(w.A0)[None]
+    ref = ops.N(At[0])[None]
+    a = make_plan(w, prec, factor_policy=2).nonlinear(to_dev(torch, At, prec)).cpu().numpy()
+    b = make_plan(w, prec, factor_policy=1).nonlinear(to_dev(torch, At, prec)).cpu().numpy()
+    print(f"[{prec}] general {relmax(a, ref):.2e} packed {relmax(b, ref):.2e}", flush=True)
+    assert relmax(a, ref) < TOL_OP[prec] and relmax(b, ref) < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_general_route_propagation_matches_oracle(torch_gpu, prec):
+    """Complex S^K != S^R, 6 modes with Raman and shock: MPA (fixed iterations,
+    a ragged last large step) and RK4IP against the oracle's."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    m, SK, SR = _general_model(w, True, True, seed=4)
+    L = 7 * w.dz
+    ref_mpa = O.mpa_propagate(w.A0, m, L, w.dz, 3, fixed_iters=3)
+    ref_rk = O.rk4ip_propagate(w.A0, m, L, w.dz)
+    plan = _general_plan(w, SK, SR, prec, fixed_iters=3)
+    e1 = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 3).field.cpu().numpy(), ref_mpa)
+    e2 = relmax(plan.propagate_rk4ip(to_dev(torch, w.A0, prec), L, w.dz).field.cpu().numpy(), ref_rk)
+    print(f"[{prec}] general route MPA {e1:.3e} RK4IP {e2:.3e}", flush=True)
+    assert e1 < TOL_PROP[prec] and e2 < TOL_PROP[prec]
