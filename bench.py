@@ -39,7 +39,7 @@ TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}
 
 
-def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0) -> dict:
+def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0, route: str = "packed") -> dict:
     """Algorithmic work of one kernel kind for one sub-step integrand: flops
     (of the unit named in "compute") and HBM bytes.
 
@@ -53,6 +53,12 @@ def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0) -> dict:
     rs = 8 if prec == "fp64" else 4        # bytes per real (a bf16 hi/lo pair is 4 bytes too)
     cs = 2 * rs
     fft = 5.0 * Nt * math.log2(Nt)
+    if route == "general":   # 4 real rows per pair; real GEMM 2 N^2 x 4 Np; one complex transform pair per pair
+        if kind == "contract":
+            return {"compute": "mfma", "flops": 2.0 * (2 * N * N) * (4 * Np) * Nt,
+                    "bytes": 4 * Np * Nt * rs + 2 * N * Nt * cs}
+        if kind == "pairs_raman":
+            return {"compute": "alu", "flops": Np * 2 * fft, "bytes": N * Nt * cs + 4 * Np * Nt * rs}
     if kind == "contract":
         k = rank if rank else Np
         return {"compute": "mfma", "flops": 2.0 * Np * k * Nt, "bytes": k * Nt * rs + 2 * N * Nt * cs}
@@ -89,10 +95,11 @@ def read_traffic(kind: str, workload: str, prec: str):
     return float(m_b.group(1))
 
 
-def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool):
+def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool, make_plan=None):
     import torch
     from paper_1708_05324_amd import gmmpa
-    plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30)
+    plan = (make_plan(prec) if make_plan else
+            gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30))
     rank = plan.rank()
     dtype = torch.complex128 if prec == "fp64" else torch.complex64
     A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
@@ -184,7 +191,8 @@ def sweep_accuracy(w, n_steps: int = 40) -> dict:
     return out
 
 
-def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str, rank: int = 0):
+def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str, rank: int = 0,
+             route: str = "packed"):
     """Roofline entry of the kernel kind with the largest total time.  The bound
     is the ceiling that takes longer for the kernel's algorithmic work: its
     flops at the compute peak (MFMA, or vector ALU for the transforms) or its
@@ -192,7 +200,7 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
     kind = max(prof, key=lambda k: prof[k][0])
     total_ms, launches = prof[kind]
     evals = stats["evaluations"]          # sub-step integrands = units processed by all counted launches
-    wk = work_per_eval(kind, N, Nt, prec, rank)
+    wk = work_per_eval(kind, N, Nt, prec, rank, route)
     sec = total_ms * 1e-3
     if wk["compute"] == "mfma":
         cpeak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else
@@ -223,8 +231,9 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
     }
 
 
-def cpu_baseline(w, max_seconds: float = 30.0):
-    """The FP64 oracle on the host: one large step (M small steps) of the workload."""
+def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
+    """The FP64 oracle on the host: large steps (M small steps each) of the same
+    workload from its launch field, until at least min_seconds of work."""
     from oracle import gmmnlse as O
     try:
         from threadpoolctl import threadpool_info
@@ -232,12 +241,19 @@ def cpu_baseline(w, max_seconds: float = 30.0):
     except Exception:
         threads = os.cpu_count() or 1
     m = O.model_from_workload(w)
+    A = w.A0
+    n_large, iters, evals = 0, 0, 0
     t0 = time.perf_counter()
-    _, st = O.mpa_propagate(w.A0, m, w.M * w.dz, w.dz, w.M, tol=TOL["fp64"], max_iter=30, return_stats=True)
+    while n_large < max_large_steps and (n_large == 0 or time.perf_counter() - t0 < min_seconds):
+        A, st = O.mpa_propagate(A, m, w.M * w.dz, w.dz, w.M, tol=TOL["fp64"], max_iter=30, return_stats=True)
+        n_large += 1
+        iters += sum(st.iterations)
+        evals += st.evaluations
     sec = time.perf_counter() - t0
-    return {"value": round(w.M / sec, 4), "unit": "small steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one large step ({w.M} small steps of {w.dz * 1e6:.2f} um) of the same workload, FP64, "
-                      f"tol 1e-12 ({st.iterations[0]} iterations, {st.evaluations} evaluations) in {sec:.1f} s"}
+    return {"value": round(n_large * w.M / sec, 4), "unit": "small steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_large} large steps ({n_large * w.M} small steps of {w.dz * 1e6:.2f} um) of the same "
+                      f"workload from its launch field, FP64, tol 1e-12 ({iters} iterations, {evals} evaluations) "
+                      f"in {sec:.1f} s"}
 
 
 def main():
@@ -254,6 +270,10 @@ def main():
                     help="only run the parallel-extent sweep M = 1..40 (M = 1 is the serial trapezoid) and the "
                          "serial RK4IP baseline on the 10-mode 2^14 workload with z_NL/dz = 200, and print its "
                          "own JSON line")
+    ap.add_argument("--general", action="store_true",
+                    help="only time the general-tensor route (complex S^K != S^R without index symmetry, as "
+                         "polarised modes give) on the 15-mode 2^14 workload, 3 iterations per large step, and "
+                         "print its own JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -287,6 +307,31 @@ def main():
             pt["speedup_vs_serial"] = round(pt["small_steps_per_s"] / base, 3)
             pt["speedup_vs_rk4ip"] = round(pt["small_steps_per_s"] / rk, 3)
         out["accuracy_fp64"] = sweep_accuracy(w)
+        print(json.dumps(out), flush=True)
+        return
+    if args.general:
+        w = synth.config3()
+        scale = float(w.S[0, 0, 0, 0])
+        SK = synth.random_general_tensor(0, w.n_modes) * scale
+        SR = synth.random_general_tensor(1, w.n_modes) * scale
+        prec = "fp32" if args.precision == "bf16x3" else args.precision
+
+        def make(p):
+            return gmmpa.Plan(w.betas, SK, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,
+                              self_steepening=w.self_steepening, precision=p, SR=SR, fixed_iters=3)
+        r = run_gpu(prec, w, max(4, args.steps // 4), max(2, args.warmup), 0, not args.no_profile, make)
+        out = {"metric": "MPA steps/s, general-tensor route (complex S^K != S^R)", "unit": "small steps/s",
+               "value": round(r["small_steps_per_s"], 2), "dtype": DTYPE[prec],
+               "config": {"workload": "grin15_raman_nt16384_general_tensor", "n_modes": w.n_modes, "nt": w.nt,
+                          "M": w.M, "iterations_per_large_step": 3, "gemm_rows": 2 * w.n_modes ** 2,
+                          "gemm_k": 2 * w.n_modes * (w.n_modes + 1)},
+               "evaluations_per_s": round(r["evaluations_per_s"], 2),
+               "ms_per_large_step": round(r["ms_per_large_step"], 4)}
+        if r["prof"]:
+            out["roofline"] = roofline(r["prof"], r["stats"], w.n_modes, w.nt, prec,
+                                       "grin15_raman_nt16384_general", 0, "general")
+        if r["breakdown"]:
+            out["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in r["breakdown"].items()}
         print(json.dumps(out), flush=True)
         return
     if args.copy_probe:
