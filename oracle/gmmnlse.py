@@ -25,6 +25,14 @@ Conventions (readings of the paper; each is pinned by a test):
     makes Eq. (8) a delay by +db1 z.  Spectrum = numpy ``ifft``, time = ``fft``;
   * the Raman convolution is circular on the window with weights
     h_R(k dt) dt renormalised to unit sum (zero-frequency gain exactly 1).
+  * saturating gain (Sec. III.F, optional): the added terms are read as
+    G_p = g_p [A_p - sum_lmn S^R_plmn A_l Phi_mn / I_sat],
+    Phi_mn = int A_m A_n^* dtau.  The paper prints the saturation term without
+    a gain factor; it comes from expanding g0 / (1 + F / F_sat) to first order
+    and projecting on the modes, which leaves the gain coefficient in front of
+    both terms (and makes the units those of g_p A_p, with I_sat a saturation
+    fluence in J/m^2).  G enters the right-hand side beside the nonlinear term,
+    without the factor i (n2 w0/c)(1 + (i/w0) d/dt).
 """
 from __future__ import annotations
 
@@ -56,6 +64,8 @@ class Model:
     omega0: float
     n2: float
     self_steepening: int = 1
+    gain: np.ndarray | None = None   # [N] small-signal field gain g_p (1/m), or None
+    I_sat: float = math.inf           # saturation fluence (J/m^2) of the gain term
 
     @property
     def n_modes(self) -> int:
@@ -137,11 +147,28 @@ def nonlinear_polarisation(A: np.ndarray, model: Model, H: np.ndarray | None) ->
     return NL
 
 
+def gain_term(A: np.ndarray, model: Model) -> np.ndarray:
+    """Saturating gain of Sec. III.F for time-domain fields A [N, Nt]:
+    G_p(t) = g_p [A_p(t) - sum_lmn S^R_plmn A_l(t) Phi_mn / I_sat],
+    Phi_mn = int A_m A_n^* dtau (a rectangle-rule sum over the window)."""
+    N = A.shape[0]
+    g = np.asarray(model.gain, dtype=float)
+    Phi = (A @ np.conj(A).T) * model.dt                           # Phi_mn = sum_t A_m A_n^* dt
+    SR = model.SR if model.SR is not None else model.SK
+    Msat = (SR.reshape(N * N, N * N) @ Phi.reshape(N * N)).reshape(N, N)   # sum_mn S^R_plmn Phi_mn
+    return g[:, None] * (A - (Msat @ A) / model.I_sat)
+
+
 def nonlinear_operator(At: np.ndarray, model: Model, omega: np.ndarray, H) -> np.ndarray:
-    """N~[A](w) = i (n2 w0 / c) (1 + s w/w0) F{NL(t)}: the integrand factor of Eq. (MPA_eq)."""
-    NL = nonlinear_polarisation(to_time(At), model, H)
+    """N~[A](w) = i (n2 w0 / c) (1 + s w/w0) F{NL(t)}: the integrand factor of Eq. (MPA_eq),
+    plus F{G} when the model has the saturating-gain term."""
+    A = to_time(At)
+    NL = nonlinear_polarisation(A, model, H)
     shock = 1.0 + (omega / model.omega0 if model.self_steepening else 0.0)
-    return 1j * model.gamma_hat * shock * to_spectrum(NL)
+    out = 1j * model.gamma_hat * shock * to_spectrum(NL)
+    if model.gain is not None:
+        out = out + to_spectrum(gain_term(A, model))
+    return out
 
 
 class _Ops:

@@ -371,3 +371,75 @@ def test_spm_xpm_terms_exchange_no_energy():
     e0 = np.sum(np.abs(A0) ** 2, axis=1)
     e1 = np.sum(np.abs(A) ** 2, axis=1)
     assert np.max(np.abs(e1 - e0) / e0) < 1e-12
+
+
+# ------------------------------------------------------------------ saturating gain (Sec. III.F)
+def _with_gain(m, g, I_sat=math.inf):
+    m.gain = np.asarray(g, float)
+    m.I_sat = I_sat
+    return m
+
+
+def test_linear_gain_follows_the_closed_forms_of_both_schemes():
+    """Gain alone (n2 = 0, I_sat infinite), with dispersion: each mode grows by
+    exp(D_w L) times the scheme's own amplification per step, exactly:
+    the converged MPA (trapezoid) by ((1 + g h/2) / (1 - g h/2))^n, RK4IP by the
+    degree-4 Taylor polynomial of exp(g h) to the power n (Sec. III.D, III.F)."""
+    nt, dt = 256, 20e-15
+    betas = [[0.0, 0.0, -0.02e-24], [300.0, 1e-12, 0.02e-24], [-50.0, -5e-13, 0.0]]
+    g = np.array([2.0, -1.0, 5.0])
+    m = _with_gain(mk(betas, dt=dt, n2=0.0), g)
+    A0 = np.stack([gauss(nt, dt, 200e-15), 0.5 * gauss(nt, dt, 150e-15, 1e-12), 0.2j * gauss(nt, dt, 300e-15)])
+    L, n = 0.05, 20
+    h = L / n
+    D = O.dispersion_operator(np.asarray(betas), O.omega_grid(nt, dt))
+    lin = np.exp(D * L) * O.to_spectrum(A0)
+    trap = ((1 + g * h / 2) / (1 - g * h / 2)) ** n
+    x = g * h
+    rk4 = (1 + x + x ** 2 / 2 + x ** 3 / 6 + x ** 4 / 24) ** n
+    got_mpa = O.mpa_propagate(A0, m, L, h, 5, tol=1e-15, max_iter=60)
+    got_rk = O.rk4ip_propagate(A0, m, L, h)
+    assert relmax(got_mpa, O.to_time(trap[:, None] * lin)) < 1e-12
+    assert relmax(got_rk, O.to_time(rk4[:, None] * lin)) < 1e-12
+
+
+def test_saturating_gain_gives_logistic_energy_growth():
+    """One mode, no dispersion or Kerr: dA/dz = g (A - S E A / I_sat) keeps the
+    pulse shape and E = int |A|^2 dt obeys dE/dz = 2 g E (1 - S E / I_sat), so
+    E(z) = E_s / (1 + (E_s/E_0 - 1) exp(-2 g z)) with E_s = I_sat / S."""
+    nt, dt = 512, 10e-15
+    S0 = 1.0 / (math.pi * synth.GrinFiber().w ** 2)
+    S = np.full((1, 1, 1, 1), S0)
+    A0 = np.sqrt(1e3) * gauss(nt, dt, 300e-15)[None]
+    E0 = O.energy(A0, dt)
+    I_sat = 5.0 * S0 * E0                                      # saturates at 5 E0
+    g = 20.0
+    m = _with_gain(mk([[0.0, 0.0, 0.0]], S=S, dt=dt, n2=0.0), [g], I_sat)
+    L = 0.1
+    A = O.rk4ip_propagate(A0, m, L, L / 400)
+    Es = I_sat / S0
+    expect = Es / (1 + (Es / E0 - 1) * math.exp(-2 * g * L))
+    assert abs(O.energy(A, dt) / expect - 1) < 1e-9
+    ratio = A[0] / A0[0]
+    mask = np.abs(A0[0]) > 1e-3 * np.abs(A0[0]).max()
+    assert np.ptp(np.abs(ratio[mask])) < 1e-9 * np.abs(ratio[mask]).mean()
+
+
+def test_gain_term_brute_force():
+    """The saturation term as written in Sec. III.F, summed index by index."""
+    rng = np.random.default_rng(11)
+    N, nt, dt = 2, 16, 1e-14
+    SK = rng.standard_normal((N,) * 4) + 1j * rng.standard_normal((N,) * 4)
+    SR = rng.standard_normal((N,) * 4)
+    A = rng.standard_normal((N, nt)) + 1j * rng.standard_normal((N, nt))
+    g = np.array([0.7, -0.3])
+    m = _with_gain(mk(np.zeros((N, 3)), S=SK, SR=SR, dt=dt), g, 3.5)
+    want = np.zeros((N, nt), complex)
+    for p in range(N):
+        for t in range(nt):
+            acc = 0j
+            for l, mm, n in itertools.product(range(N), repeat=3):
+                phi = sum(A[mm, u] * np.conj(A[n, u]) for u in range(nt)) * dt
+                acc += SR[p, l, mm, n] * A[l, t] * phi
+            want[p, t] = g[p] * (A[p, t] - acc / 3.5)
+    assert relmax(O.gain_term(A, m), want) < 1e-13
