@@ -143,6 +143,20 @@ int gmm_propagate(gmm_plan plan, const void* A0, double L, double dz, int M, voi
 int gmm_propagate_rk4ip(gmm_plan plan, const void* A0, double L, double dz, void* Aout, gmm_stats* st);
 
 /*
+ * gmm_plan_set_gain - turn on the saturating-gain term of Sec. III.F,
+ *   G_p = g_p [A_p - sum_lmn S^R_plmn A_l int A_m A_n^* dtau / I_sat],
+ * which every later propagate (MPA and RK4IP) and gmm_nonlinear add to the
+ * right-hand side beside the nonlinear term (without its factor
+ * i (n2 w0/c)(1 + (i/w0) d/dt)).  S^R is the plan's Raman tensor (S^K when it
+ * was created with SR = NULL).
+ *   g     : host [N] small-signal field gain per mode (1/m), copied; NULL turns
+ *           the term off.
+ *   I_sat : saturation fluence (J/m^2) > 0; INFINITY for unsaturated gain.
+ * Returns GMM_ERR_ARG for bad values, GMM_ERR_UNSUPPORTED above 22 modes.
+ */
+int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat);
+
+/*
  * gmm_nonlinear - the integrand factor of Eq. (MPA_eq) for `count` fields:
  *   out_c(w) = i (n2 w0/c) (1 + s w/w0) F{ sum_lmn [(1-fR) S_plmn A_l A_m A_n^*
  *                                            + fR S_plmn A_l (h_R * A_m A_n^*)] }
@@ -183,7 +197,8 @@ int gmm_plan_rank(gmm_plan plan);
 #define GMM_PROF_NORM 5     /* norm reduction + stop decision */
 #define GMM_PROF_CLOSE 6    /* large-step close */
 #define GMM_PROF_PROJECT 7  /* rank-r route: Y = V B on MFMA (pair products formed on the fly) */
-#define GMM_PROF_KINDS 8
+#define GMM_PROF_GAIN 8     /* saturating gain: pair integrals, gain matrices, spectral update */
+#define GMM_PROF_KINDS 9
 #define GMM_PROF_ALL ((1 << GMM_PROF_KINDS) - 1)
 int gmm_profile_enable(gmm_plan plan, int kinds);
 int gmm_profile_read(gmm_plan plan, double* total_ms, long long* launches, int n_kinds);

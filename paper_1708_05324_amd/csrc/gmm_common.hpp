@@ -16,6 +16,11 @@ struct Ctrl {
 };
 
 
+// Most modes the saturating-gain kernels take (their N x N matrices sit in LDS),
+// and the samples per partial sum of the pair integrals.
+constexpr int kGainNmax = 22;
+constexpr int kGainChunkHost = 128;
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cplx {
   T re, im;

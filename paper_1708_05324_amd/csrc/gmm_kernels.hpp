@@ -1285,6 +1285,81 @@ __global__ __launch_bounds__(256) void k_rk4ip_stage(int stage, cplx<T>* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Saturating gain (Sec. III.F), added to the integrand beside the nonlinear term:
+//   G_p(t) = g_p [A_p(t) - sum_lmn S^R_plmn A_l(t) Phi_mn / I_sat],
+//   Phi_mn = int A_m A_n^* dtau,
+// i.e. G = Mg A with the per-sub-step N x N matrix
+//   Mg_pl = g_p [delta_pl - (1/I_sat) sum_mn S^R_plmn Phi_mn].
+// G is linear in A with a time-independent matrix, so it is applied to the
+// spectra: I_j += exp(-D_w z_j) Mg (exp(D_w z_j) psi_j).
+//
+// k_pair_integrals: partial sums of A_m(t) A_n^*(t) over 128-sample chunks, in
+// FP64.  grid (Nt / 128, count); the chunk's fields are staged in LDS and each
+// thread sums whole (m, n) entries.  Out: [count][chunks][N][N] complex.
+constexpr int kGainChunk = kGainChunkHost;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_integrals(const cplx<T>* __restrict__ A, cplx<double>* __restrict__ part,
+                                                        int N, int Nt, const Ctrl* ctrl) {
+  if (skip_iteration(ctrl)) return;
+  __shared__ cplx<T> sA[kGainNmax * kGainChunk];
+  const int tid = threadIdx.x, c = blockIdx.x, jj = blockIdx.y, C = gridDim.x;
+  const cplx<T>* Aj = A + (size_t)jj * N * Nt + (size_t)c * kGainChunk;
+  for (int i = tid; i < N * kGainChunk; i += 256) {
+    const int l = i / kGainChunk, t = i - l * kGainChunk;
+    sA[i] = Aj[(size_t)l * Nt + t];
+  }
+  __syncthreads();
+  for (int q = tid; q < N * N; q += 256) {
+    const int m = q / N, n = q - m * N;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < kGainChunk; ++t) {
+      const cplx<T> a = sA[m * kGainChunk + t], b = sA[n * kGainChunk + t];
+      re += (double)a.re * b.re + (double)a.im * b.im;
+      im += (double)a.im * b.re - (double)a.re * b.im;
+    }
+    part[(((size_t)jj * C + c) * N + m) * N + n] = cplx<double>{re, im};
+  }
+}
+
+// k_gain_add: out_jp(w) += conj(E_jp(w)) sum_l Mg_pl E_jl(w) psi_jl(w)
+// (E = nullptr: no phase).  grid (Nt / 256, count).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gain_add(const cplx<T>* __restrict__ psi, long psi_jrows,
+                                                  const cplx<T>* __restrict__ E, int j0,
+                                                  const cplx<double>* __restrict__ Mg, cplx<T>* __restrict__ out,
+                                                  int N, int Nt, const Ctrl* ctrl) {
+  if (skip_iteration(ctrl)) return;
+  __shared__ cplx<T> sM[kGainNmax * kGainNmax];
+  const int tid = threadIdx.x, jj = blockIdx.y, k = blockIdx.x * 256 + tid;
+  for (int q = tid; q < N * N; q += 256) {
+    const cplx<double> v = Mg[(size_t)jj * N * N + q];
+    sM[q] = cplx<T>{(T)v.re, (T)v.im};
+  }
+  __syncthreads();
+  cplx<T> a[kGainNmax];
+#pragma unroll
+  for (int l = 0; l < kGainNmax; ++l) {
+    if (l < N) {
+      const cplx<T> x = psi[((size_t)jj * psi_jrows + l) * Nt + k];
+      a[l] = E != nullptr ? cmul(E[((size_t)(j0 + jj) * N + l) * Nt + k], x) : x;
+    }
+  }
+  for (int p = 0; p < N; ++p) {
+    cplx<T> gsum = {T(0), T(0)};
+#pragma unroll
+    for (int l = 0; l < kGainNmax; ++l)
+      if (l < N) gsum = cadd(gsum, cmul(sM[p * N + l], a[l]));
+    if (E != nullptr) {
+      const cplx<T> e = E[((size_t)(j0 + jj) * N + p) * Nt + k];
+      gsum = cmul(gsum, cplx<T>{e.re, -e.im});
+    }
+    cplx<T>& o = out[((size_t)jj * N + p) * Nt + k];
+    o = cadd(o, gsum);
+  }
+}
+
 // FP64 spectral sums for the bookkeeping: sum |A~|^2 and sum |A~|^2 / (w0 + w).
 template <typename T>
 __global__ __launch_bounds__(256) void k_spec_sums(const cplx<T>* __restrict__ At, int nt, long nn, double domega,

@@ -40,6 +40,12 @@ struct Launch {
                                 hipStream_t s);
   static hipError_t contract_dense(const T* G, const T* Bd, cplx<T>* A_NL, int N, int KD, int rows_pad, int Nt,
                                    int count, const Ctrl* ctrl, hipStream_t s);
+  // Saturating gain: pair integrals of the time-domain fields (chunk partials), then
+  // out += E^-1 Mg E psi for the spectra (Mg built by launch_gain_matrix).
+  static hipError_t pair_integrals(const cplx<T>* A, cplx<double>* part, int N, int Nt, int count, const Ctrl* ctrl,
+                                   hipStream_t s);
+  static hipError_t gain_add(const cplx<T>* psi, long psi_jrows, const cplx<T>* E, int j0, const cplx<double>* Mg,
+                             cplx<T>* out, int N, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
   // Element-wise part of one RK4IP stage (1..4) over nn elements.
   static hipError_t rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
                                 const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,
@@ -73,6 +79,10 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+// Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn), Phi = dt * sum of the chunk partials.
+hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double>* SR, const double* g,
+                              double inv_Isat, double dt, cplx<double>* Mg, int N, int count, const Ctrl* ctrl,
+                              hipStream_t s);
 
 inline int contract_max_rows() { return 256; }
 inline int trapz_blocks(long nn) { return (int)((nn + 255) / 256); }

@@ -245,6 +245,24 @@ hipError_t Launch<T>::contract_dense(const T* G, const T* Bd, cplx<T>* A_NL, int
 }
 
 template <typename T>
+hipError_t Launch<T>::pair_integrals(const cplx<T>* A, cplx<double>* part, int N, int Nt, int count,
+                                     const Ctrl* ctrl, hipStream_t s) {
+  if (N > kGainNmax || Nt % kGainChunk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_pair_integrals<T>), dim3(Nt / kGainChunk, count), dim3(256), 0, s, A, part, N, Nt, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::gain_add(const cplx<T>* psi, long psi_jrows, const cplx<T>* E, int j0,
+                               const cplx<double>* Mg, cplx<T>* out, int N, int Nt, int count, const Ctrl* ctrl,
+                               hipStream_t s) {
+  if (N > kGainNmax || Nt % 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gain_add<T>), dim3(Nt / 256, count), dim3(256), 0, s, psi, psi_jrows, E, j0, Mg, out, N, Nt,
+                     ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::rk4ip_stage(int stage, cplx<T>* At, cplx<T>* AI, cplx<T>* k1, const cplx<T>* k2,
                                   const cplx<T>* k3, const cplx<T>* k4, cplx<T>* X, const cplx<T>* Eh, T h, long nn,
                                   hipStream_t s) {

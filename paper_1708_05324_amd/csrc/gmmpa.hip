@@ -162,6 +162,15 @@ struct gmm_plan_s {
   bool dense = false;
   int KD = 0, rows_pad = 0;  // real pair rows per sub-step (multiple of 4); output rows 2 N^2 padded to 64
   void* G = nullptr;         // [rows_pad][KD] real coupling matrix of the general route, field precision
+  // saturating gain (Sec. III.F): G = Mg A per sub-step
+  std::vector<std::complex<double>> SRh;  // host copy of S^R (S^K when SR is NULL), [N^4]
+  bool gain_on = false;
+  double inv_Isat = 0.0;
+  double* gvec = nullptr;               // [N] g_p (1/m)
+  cplx<double>* SRd = nullptr;          // [N^4] S^R on the device
+  cplx<double>* gpart = nullptr;        // workspace [cap][Nt/256][N][N] pair-integral partials
+  cplx<double>* Mg = nullptr;           // workspace [cap][N][N]
+  int gain_cap = 0;
   int* pidx = nullptr;     // [N][N]
   int2* pairs = nullptr;   // [Np]
   // workspace
@@ -205,6 +214,29 @@ void free_workspace(gmm_plan_s* P) {
 }
 
 size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->esz; }
+
+// Pair-integral partials and gain matrices for `cap` sub-steps (only with the gain term on).
+int ensure_gain_workspace(gmm_plan_s* P, int cap) {
+  if (!P->gain_on || cap <= P->gain_cap) return GMM_OK;
+  for (cplx<double>** q : {&P->gpart, &P->Mg}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  P->gain_cap = 0;
+  const size_t nn = (size_t)P->N * P->N;
+  void* a = nullptr;
+  void* b = nullptr;
+  if (hipMalloc(&a, (size_t)cap * (P->nt / gmm::kGainChunkHost) * nn * sizeof(cplx<double>)) != hipSuccess ||
+      hipMalloc(&b, (size_t)cap * nn * sizeof(cplx<double>)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipFree(a);
+    return fail(GMM_ERR_NOMEM, "hipMalloc of the gain workspace failed");
+  }
+  P->gpart = (cplx<double>*)a;
+  P->Mg = (cplx<double>*)b;
+  P->gain_cap = cap;
+  return GMM_OK;
+}
 
 // B' for `cap` sub-steps: [cap][Np][Nt] reals, or two bf16 planes [cap][Kpad/8][Nt][8].
 size_t bp_bytes(const gmm_plan_s* P, int cap) {
@@ -260,6 +292,13 @@ struct Runner {
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
                                                          P->stream));
+    if (P->gain_on) {  // pair integrals of the sub-step fields, then the gain matrices
+      if (count > P->gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
+      GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_GAIN, gmm::launch_gain_matrix(P->gpart, P->nt / gmm::kGainChunkHost, P->SRd, P->gvec,
+                                                           P->inv_Isat,
+                                                           P->prm.dt, P->Mg, P->N, count, ctrl, P->stream));
+    }
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
       GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
                                                            count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
@@ -317,6 +356,9 @@ struct Runner {
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, E, P->N, count, j0, P->domega,
                                                            P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
                                                            P->prm.self_steepening, tw(), ctrl, P->stream));
+    if (P->gain_on)
+      GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::gain_add(psi, jrows, E, j0, P->Mg, out, P->N, P->nt, count, ctrl,
+                                                       P->stream));
     return GMM_OK;
   }
 
@@ -386,6 +428,7 @@ struct Runner {
     const double dz = L / (double)n_small;
     int rc = ensure_workspace(P, M + 1);  // the first iteration also evaluates sub-step 0
     if (rc) return rc;
+    if ((rc = ensure_gain_workspace(P, M + 1))) return rc;
     if ((rc = ensure_phase_table(M + 1, dz))) return rc;
     gmm_stats s{};
     s.dz_used = dz;
@@ -471,6 +514,7 @@ struct Runner {
     const double h = L / (double)n_small;
     int rc = ensure_workspace(P, 6);  // AI, k1..k4, X in the sub-step rows
     if (rc) return rc;
+    if ((rc = ensure_gain_workspace(P, 1))) return rc;
     if ((rc = ensure_phase_table(2, 0.5 * h))) return rc;  // row 1: exp(D h/2)
     gmm_stats s{};
     s.dz_used = h;
@@ -506,6 +550,7 @@ struct Runner {
   int nonlinear(const void* At, int count, void* out) {
     int rc = ensure_workspace(P, count);
     if (rc) return rc;
+    if ((rc = ensure_gain_workspace(P, count))) return rc;
     P->prof.cur_iter = 0;
     rc = eval((const cplx<T>*)At, P->N, count, 0, 0.0, (cplx<T>*)out, nullptr);
     if (rc == GMM_OK && P->prof.on) {
@@ -767,7 +812,7 @@ void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
-                  P->G, (void*)P->pidx,
+                  P->G, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
@@ -867,6 +912,8 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   P->raman = raman;
   P->esz = fp64 ? 8 : 4;
   P->dense = dense;
+  P->SRh.resize(n4);
+  for (size_t i = 0; i < n4; ++i) P->SRh[i] = sr(i);
 
   int rc = GMM_OK;
   auto bail = [&](int code) {
@@ -979,6 +1026,31 @@ int gmm_propagate_rk4ip(gmm_plan plan, const void* A0, double L, double dz, void
   } catch (...) {
     return fail(GMM_ERR_NOMEM, "host allocation failed");
   }
+}
+
+int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  if (!g) {
+    plan->gain_on = false;
+    return GMM_OK;
+  }
+  if (!(I_sat > 0)) return fail(GMM_ERR_ARG, "I_sat must be > 0 (infinity: no saturation)");
+  if (plan->N > gmm::kGainNmax) return fail(GMM_ERR_UNSUPPORTED, "the gain term supports up to 22 modes");
+  for (int p = 0; p < plan->N; ++p)
+    if (!std::isfinite(g[p])) return fail(GMM_ERR_ARG, "non-finite gain coefficient");
+  const size_t n4 = plan->SRh.size();
+  if (!plan->gvec && (dev_alloc(&plan->const_bytes, &plan->gvec, plan->N * sizeof(double)) ||
+                      dev_alloc(&plan->const_bytes, &plan->SRd, n4 * sizeof(cplx<double>))))
+    return GMM_ERR_NOMEM;
+  std::vector<cplx<double>> sr(n4);
+  for (size_t i = 0; i < n4; ++i) sr[i] = cplx<double>{plan->SRh[i].real(), plan->SRh[i].imag()};
+  if (hipMemcpy(plan->gvec, g, plan->N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(plan->SRd, sr.data(), n4 * sizeof(cplx<double>), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(GMM_ERR_HIP, "copy of the gain constants failed");
+  plan->inv_Isat = std::isinf(I_sat) ? 0.0 : 1.0 / I_sat;
+  plan->gain_on = true;
+  g_last_error.clear();
+  return GMM_OK;
 }
 
 int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out) {

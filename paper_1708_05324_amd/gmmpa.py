@@ -28,9 +28,11 @@ GMM_FP64 = 0
 GMM_FP32 = 1
 GMM_BF16X3 = 2
 
-EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_nonlinear", "gmm_plan_destroy",
-           "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable", "gmm_profile_read")
-PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project")
+EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_plan_set_gain", "gmm_nonlinear",
+           "gmm_plan_destroy", "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable",
+           "gmm_profile_read")
+PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project",
+                 "gain")
 
 
 class gmm_params(ctypes.Structure):
@@ -71,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_propagate.restype = ci
     lib.gmm_propagate_rk4ip.argtypes = [vp, vp, dbl, dbl, vp, ctypes.POINTER(gmm_stats)]
     lib.gmm_propagate_rk4ip.restype = ci
+    lib.gmm_plan_set_gain.argtypes = [vp, vp, dbl]
+    lib.gmm_plan_set_gain.restype = ci
     lib.gmm_nonlinear.argtypes = [vp, vp, ci, vp]
     lib.gmm_nonlinear.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
@@ -188,6 +192,16 @@ class Plan:
                                           ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
         _check(rc)
         return Result(out, rc, st.as_dict())
+
+    def set_gain(self, g=None, I_sat: float = float("inf")):
+        """Saturating gain of Sec. III.F: g [N] small-signal field gain (1/m), or None to turn it off;
+        I_sat the saturation fluence (J/m^2)."""
+        if g is None:
+            _check(self.lib.gmm_plan_set_gain(self.handle, None, float(I_sat)))
+            return
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(self.n_modes))
+        self._gain = g
+        _check(self.lib.gmm_plan_set_gain(self.handle, _host_ptr(g), float(I_sat)))
 
     def nonlinear(self, At, out=None):
         """Integrand factor of Eq. (MPA_eq) for spectra At [count][N][Nt]."""

@@ -351,3 +351,82 @@ def test_general_route_propagation_matches_oracle(torch_gpu, prec):
     e2 = relmax(plan.propagate_rk4ip(to_dev(torch, w.A0, prec), L, w.dz).field.cpu().numpy(), ref_rk)
     print(f"[{prec}] general route MPA {e1:.3e} RK4IP {e2:.3e}", flush=True)
     assert e1 < TOL_PROP[prec] and e2 < TOL_PROP[prec]
+
+
+def _gain_setup(w, seed=5, sat=2.0):
+    """Per-mode field gains of a few 1/m and a saturation fluence that makes the
+    saturation term comparable to the small-signal term for this pulse."""
+    rng = np.random.default_rng(synth.SEED_BASE + 4000 + seed)
+    g = rng.uniform(0.5, 3.0, w.n_modes)
+    E = float(np.sum(np.abs(w.A0) ** 2) * w.dt)
+    I_sat = float(w.S[0, 0, 0, 0]) * E * sat
+    return g, I_sat
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", [(2, 256, 0.0, 1), (3, 1024, 0.18, 0), (5, 1024, 0.18, 0), (3, 512, 0.18, 2)],
+                         ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_policy{c[3]}")
+def test_gain_operator_matches_oracle(torch_gpu, prec, case):
+    """Saturating gain of Sec. III.F added to the operator, through the packed,
+    rank-r and general routes, against the oracle."""
+    torch = torch_gpu
+    g_, nt, fR, policy = case
+    w = small_workload(N_groups=g_, nt=nt, fR=fR, s=1, dt=20480e-15 / nt)
+    g, I_sat = _gain_setup(w)
+    m = O.model_from_workload(w)
+    m.gain, m.I_sat = g, I_sat
+    ops = O._Ops(m, w.nt)
+    spectra = [O.to_spectrum(w.A0 * (1 + 0.5 * c)) for c in range(2)]
+    ref = np.stack([ops.N(a) for a in spectra])
+    plan = make_plan(w, prec, factor_policy=policy)
+    plan.set_gain(g, I_sat)
+    got = plan.nonlinear(to_dev(torch, np.stack(spectra), prec)).cpu().numpy()
+    err = relmax(got, ref)
+    print(f"[{prec} {case}] gain operator error {err:.3e} rank {plan.rank()}", flush=True)
+    assert err < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gain_propagation_matches_oracle(torch_gpu, prec):
+    """6 modes with Raman, shock and saturating gain: MPA (fixed iterations, a
+    ragged last large step) and RK4IP against the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    g, I_sat = _gain_setup(w, sat=1.0)
+    m = O.model_from_workload(w)
+    m.gain, m.I_sat = g * 20.0, I_sat
+    L = 7 * w.dz
+    ref_mpa = O.mpa_propagate(w.A0, m, L, w.dz, 3, fixed_iters=3)
+    ref_rk = O.rk4ip_propagate(w.A0, m, L, w.dz)
+    plan = make_plan(w, prec, fixed_iters=3)
+    plan.set_gain(g * 20.0, I_sat)
+    e1 = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 3).field.cpu().numpy(), ref_mpa)
+    e2 = relmax(plan.propagate_rk4ip(to_dev(torch, w.A0, prec), L, w.dz).field.cpu().numpy(), ref_rk)
+    print(f"[{prec}] gain MPA {e1:.3e} RK4IP {e2:.3e}", flush=True)
+    assert e1 < TOL_PROP[prec] and e2 < TOL_PROP[prec]
+    plan.set_gain(None)                       # off again: plain propagation
+    e3 = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 3).field.cpu().numpy(),
+                O.mpa_propagate(w.A0, O.model_from_workload(w), L, w.dz, 3, fixed_iters=3))
+    assert e3 < TOL_PROP[prec]
+
+
+def test_gain_saturates_logistically_on_gpu(torch_gpu):
+    """One mode, no dispersion or Kerr: the GPU RK4IP energy follows the
+    logistic closed form E_s / (1 + (E_s/E_0 - 1) exp(-2 g z))."""
+    torch = torch_gpu
+    from paper_1708_05324_amd import gmmpa
+    nt, dt = 1024, 10e-15
+    S0 = 1.0 / (math.pi * synth.GrinFiber().w ** 2)
+    t = synth.time_grid(nt, dt)
+    A0 = (np.sqrt(1e3) * np.exp(-t ** 2 / (2 * (300e-15) ** 2)) + 0j)[None]
+    E0 = float(np.sum(np.abs(A0) ** 2) * dt)
+    I_sat, g, L = 5.0 * S0 * E0, 20.0, 0.1
+    plan = gmmpa.Plan(np.zeros((1, 3)), np.full((1, 1, 1, 1), S0), None, nt=nt, dt=dt,
+                      omega0=synth.GrinFiber().omega0, n2=0.0, fR=0.0, self_steepening=0, precision="fp64")
+    plan.set_gain([g], I_sat)
+    A = plan.propagate_rk4ip(to_dev(torch, A0, "fp64"), L, L / 400).field.cpu().numpy()
+    Es = I_sat / S0
+    expect = Es / (1 + (Es / E0 - 1) * math.exp(-2 * g * L))
+    got = float(np.sum(np.abs(A) ** 2) * dt)
+    print(f"logistic energy {got:.6e} expected {expect:.6e}", flush=True)
+    assert abs(got / expect - 1) < 1e-9
