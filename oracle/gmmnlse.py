@@ -33,6 +33,10 @@ Conventions (readings of the paper; each is pinned by a test):
     both terms (and makes the units those of g_p A_p, with I_sat a saturation
     fluence in J/m^2).  G enters the right-hand side beside the nonlinear term,
     without the factor i (n2 w0/c)(1 + (i/w0) d/dt).
+  * linear mode coupling (Sec. III.F, optional): the added term
+    C_p = i sum_n Q_np A_n with a z-independent coupling matrix Q, also beside
+    the nonlinear term (so the MPA treats it inside its integrand, which needs
+    L = M dz << 1/|Q|, the same regime as for the nonlinear length).
 """
 from __future__ import annotations
 
@@ -66,6 +70,7 @@ class Model:
     self_steepening: int = 1
     gain: np.ndarray | None = None   # [N] small-signal field gain g_p (1/m), or None
     I_sat: float = math.inf           # saturation fluence (J/m^2) of the gain term
+    Q: np.ndarray | None = None      # [N, N] linear coupling Q_np (1/m), C_p = i sum_n Q_np A_n, or None
 
     @property
     def n_modes(self) -> int:
@@ -161,13 +166,15 @@ def gain_term(A: np.ndarray, model: Model) -> np.ndarray:
 
 def nonlinear_operator(At: np.ndarray, model: Model, omega: np.ndarray, H) -> np.ndarray:
     """N~[A](w) = i (n2 w0 / c) (1 + s w/w0) F{NL(t)}: the integrand factor of Eq. (MPA_eq),
-    plus F{G} when the model has the saturating-gain term."""
+    plus F{G} when the model has the saturating-gain term and F{C} with linear mode coupling."""
     A = to_time(At)
     NL = nonlinear_polarisation(A, model, H)
     shock = 1.0 + (omega / model.omega0 if model.self_steepening else 0.0)
     out = 1j * model.gamma_hat * shock * to_spectrum(NL)
     if model.gain is not None:
         out = out + to_spectrum(gain_term(A, model))
+    if model.Q is not None:
+        out = out + 1j * (np.asarray(model.Q).T @ At)          # C_p = i sum_n Q_np A~_n (linear in A)
     return out
 
 
