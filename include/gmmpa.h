@@ -157,6 +157,18 @@ int gmm_propagate_rk4ip(gmm_plan plan, const void* A0, double L, double dz, void
 int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat);
 
 /*
+ * gmm_plan_set_coupling - turn on linear mode coupling (Sec. III.F), the term
+ *   C_p = i sum_n Q_np A_n
+ * with a z-independent coupling matrix, added like the gain term beside the
+ * nonlinear term (the MPA then needs L = M dz << 1/|Q| to converge quickly).
+ *   Q         : host [N][N] coupling coefficients (1/m), Q[n*N + p] = Q_np;
+ *               real, or complex when q_complex = 1 ([N][N][2] doubles).
+ *               Copied.  NULL turns the term off.
+ * Returns GMM_ERR_ARG for bad values, GMM_ERR_UNSUPPORTED above 22 modes.
+ */
+int gmm_plan_set_coupling(gmm_plan plan, const double* Q, int q_complex);
+
+/*
  * gmm_nonlinear - the integrand factor of Eq. (MPA_eq) for `count` fields:
  *   out_c(w) = i (n2 w0/c) (1 + s w/w0) F{ sum_lmn [(1-fR) S_plmn A_l A_m A_n^*
  *                                            + fR S_plmn A_l (h_R * A_m A_n^*)] }
@@ -197,7 +209,7 @@ int gmm_plan_rank(gmm_plan plan);
 #define GMM_PROF_NORM 5     /* norm reduction + stop decision */
 #define GMM_PROF_CLOSE 6    /* large-step close */
 #define GMM_PROF_PROJECT 7  /* rank-r route: Y = V B on MFMA (pair products formed on the fly) */
-#define GMM_PROF_GAIN 8     /* saturating gain: pair integrals, gain matrices, spectral update */
+#define GMM_PROF_GAIN 8     /* saturating gain and linear coupling: pair integrals, matrices, spectral update */
 #define GMM_PROF_KINDS 9
 #define GMM_PROF_ALL ((1 << GMM_PROF_KINDS) - 1)
 int gmm_profile_enable(gmm_plan plan, int kinds);

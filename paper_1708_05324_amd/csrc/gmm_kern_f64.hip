@@ -60,44 +60,57 @@ hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, do
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, partials, nblocks, ctrl, tol, fixed_iters, max_iter);
   return hipGetLastError();
 }
-// k_gain_matrix: Phi = dt * (sum of the chunk partials, fixed order), then
-// Mg_pl = g_p (delta_pl - inv_Isat * sum_mn S^R_plmn Phi_mn).  grid (count).
+// k_gain_matrix: the per-sub-step matrix of the linear-in-A terms of Sec. III.F,
+//   Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn)   (g != nullptr)
+//         + K_pl                                                (K != nullptr)
+// with Phi = dt * (sum of the chunk partials, fixed order) and K_pl = i Q_lp
+// the linear mode coupling.  grid (count).
 __global__ __launch_bounds__(256) void k_gain_matrix(const cplx<double>* __restrict__ part, int C,
                                                      const cplx<double>* __restrict__ SR,
                                                      const double* __restrict__ g, double inv_Isat, double dt,
+                                                     const cplx<double>* __restrict__ K,
                                                      cplx<double>* __restrict__ Mg, int N, const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
   __shared__ cplx<double> sPhi[kGainNmax * kGainNmax];
   const int tid = threadIdx.x, jj = blockIdx.x, NN = N * N;
-  for (int q = tid; q < NN; q += 256) {
-    double re = 0.0, im = 0.0;
-    for (int c = 0; c < C; ++c) {
-      const cplx<double> v = part[((size_t)jj * C + c) * NN + q];
-      re += v.re;
-      im += v.im;
+  if (g != nullptr && inv_Isat != 0.0) {
+    for (int q = tid; q < NN; q += 256) {
+      double re = 0.0, im = 0.0;
+      for (int c = 0; c < C; ++c) {
+        const cplx<double> v = part[((size_t)jj * C + c) * NN + q];
+        re += v.re;
+        im += v.im;
+      }
+      sPhi[q] = cplx<double>{re * dt, im * dt};
     }
-    sPhi[q] = cplx<double>{re * dt, im * dt};
   }
   __syncthreads();
   for (int q = tid; q < NN; q += 256) {
     const int p = q / N, l = q - p * N;
-    const cplx<double>* srow = SR + (size_t)q * NN;   // S^R_plmn, (m, n) contiguous
-    double re = 0.0, im = 0.0;
-    for (int mn = 0; mn < NN; ++mn) {
-      const cplx<double> a = srow[mn], b = sPhi[mn];
-      re += a.re * b.re - a.im * b.im;
-      im += a.re * b.im + a.im * b.re;
+    cplx<double> m = K != nullptr ? K[q] : cplx<double>{0.0, 0.0};
+    if (g != nullptr) {
+      double re = 0.0, im = 0.0;
+      if (inv_Isat != 0.0) {
+        const cplx<double>* srow = SR + (size_t)q * NN;   // S^R_plmn, (m, n) contiguous
+        for (int mn = 0; mn < NN; ++mn) {
+          const cplx<double> a = srow[mn], b = sPhi[mn];
+          re += a.re * b.re - a.im * b.im;
+          im += a.re * b.im + a.im * b.re;
+        }
+      }
+      const double d = p == l ? 1.0 : 0.0;
+      m.re += g[p] * (d - inv_Isat * re);
+      m.im -= g[p] * inv_Isat * im;
     }
-    const double d = p == l ? 1.0 : 0.0;
-    Mg[(size_t)jj * NN + q] = cplx<double>{g[p] * (d - inv_Isat * re), -g[p] * inv_Isat * im};
+    Mg[(size_t)jj * NN + q] = m;
   }
 }
 
 hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double>* SR, const double* g,
-                              double inv_Isat, double dt, cplx<double>* Mg, int N, int count, const Ctrl* ctrl,
-                              hipStream_t s) {
+                              double inv_Isat, double dt, const cplx<double>* K, cplx<double>* Mg, int N, int count,
+                              const Ctrl* ctrl, hipStream_t s) {
   if (N > kGainNmax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gain_matrix, dim3(count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, Mg, N, ctrl);
+  hipLaunchKernelGGL(k_gain_matrix, dim3(count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, K, Mg, N, ctrl);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s) {

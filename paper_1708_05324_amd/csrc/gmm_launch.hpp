@@ -79,10 +79,11 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
-// Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn), Phi = dt * sum of the chunk partials.
+// Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn) (g may be NULL) + K_pl (K may be NULL),
+// Phi = dt * sum of the chunk partials.
 hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double>* SR, const double* g,
-                              double inv_Isat, double dt, cplx<double>* Mg, int N, int count, const Ctrl* ctrl,
-                              hipStream_t s);
+                              double inv_Isat, double dt, const cplx<double>* K, cplx<double>* Mg, int N, int count,
+                              const Ctrl* ctrl, hipStream_t s);
 
 inline int contract_max_rows() { return 256; }
 inline int trapz_blocks(long nn) { return (int)((nn + 255) / 256); }

@@ -165,6 +165,8 @@ struct gmm_plan_s {
   // saturating gain (Sec. III.F): G = Mg A per sub-step
   std::vector<std::complex<double>> SRh;  // host copy of S^R (S^K when SR is NULL), [N^4]
   bool gain_on = false;
+  bool coupling_on = false;          // linear mode coupling C_p = i sum_n Q_np A_n
+  cplx<double>* Kc = nullptr;        // [N][N] K_pl = i Q_lp
   double inv_Isat = 0.0;
   double* gvec = nullptr;               // [N] g_p (1/m)
   cplx<double>* SRd = nullptr;          // [N^4] S^R on the device
@@ -217,7 +219,7 @@ size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->e
 
 // Pair-integral partials and gain matrices for `cap` sub-steps (only with the gain term on).
 int ensure_gain_workspace(gmm_plan_s* P, int cap) {
-  if (!P->gain_on || cap <= P->gain_cap) return GMM_OK;
+  if (!(P->gain_on || P->coupling_on) || cap <= P->gain_cap) return GMM_OK;
   for (cplx<double>** q : {&P->gpart, &P->Mg}) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -292,12 +294,15 @@ struct Runner {
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
     GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
                                                          P->stream));
-    if (P->gain_on) {  // pair integrals of the sub-step fields, then the gain matrices
+    const bool linear_terms = P->gain_on || P->coupling_on;
+    if (linear_terms) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
       if (count > P->gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
-      GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
-      GMM_LAUNCH(P, GMM_PROF_GAIN, gmm::launch_gain_matrix(P->gpart, P->nt / gmm::kGainChunkHost, P->SRd, P->gvec,
-                                                           P->inv_Isat,
-                                                           P->prm.dt, P->Mg, P->N, count, ctrl, P->stream));
+      if (P->gain_on && P->inv_Isat != 0.0)
+        GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_GAIN,
+                 gmm::launch_gain_matrix(P->gpart, P->nt / gmm::kGainChunkHost, P->SRd,
+                                         P->gain_on ? P->gvec : nullptr, P->inv_Isat, P->prm.dt,
+                                         P->coupling_on ? P->Kc : nullptr, P->Mg, P->N, count, ctrl, P->stream));
     }
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
       GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
@@ -356,7 +361,7 @@ struct Runner {
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, E, P->N, count, j0, P->domega,
                                                            P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
                                                            P->prm.self_steepening, tw(), ctrl, P->stream));
-    if (P->gain_on)
+    if (linear_terms)
       GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::gain_add(psi, jrows, E, j0, P->Mg, out, P->N, P->nt, count, ctrl,
                                                        P->stream));
     return GMM_OK;
@@ -812,7 +817,8 @@ void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
-                  P->G, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->pidx,
+                  P->G, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
+                  (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
@@ -1049,6 +1055,31 @@ int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat) {
     return fail(GMM_ERR_HIP, "copy of the gain constants failed");
   plan->inv_Isat = std::isinf(I_sat) ? 0.0 : 1.0 / I_sat;
   plan->gain_on = true;
+  g_last_error.clear();
+  return GMM_OK;
+}
+
+int gmm_plan_set_coupling(gmm_plan plan, const double* Q, int q_complex) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  if (!Q) {
+    plan->coupling_on = false;
+    return GMM_OK;
+  }
+  if (q_complex != 0 && q_complex != 1) return fail(GMM_ERR_ARG, "q_complex must be 0 or 1");
+  const int N = plan->N;
+  if (N > gmm::kGainNmax) return fail(GMM_ERR_UNSUPPORTED, "linear coupling supports up to 22 modes");
+  std::vector<cplx<double>> K((size_t)N * N);
+  for (int n = 0; n < N; ++n)
+    for (int p = 0; p < N; ++p) {
+      const size_t i = (size_t)n * N + p;  // Q_np: coefficient of A_n in the equation of mode p
+      const double re = q_complex ? Q[2 * i] : Q[i], im = q_complex ? Q[2 * i + 1] : 0.0;
+      if (!std::isfinite(re) || !std::isfinite(im)) return fail(GMM_ERR_ARG, "non-finite coupling coefficient");
+      K[(size_t)p * N + n] = cplx<double>{-im, re};  // K_pn = i Q_np
+    }
+  if (!plan->Kc && dev_alloc(&plan->const_bytes, &plan->Kc, K.size() * sizeof(cplx<double>))) return GMM_ERR_NOMEM;
+  if (hipMemcpy(plan->Kc, K.data(), K.size() * sizeof(cplx<double>), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(GMM_ERR_HIP, "copy of the coupling matrix failed");
+  plan->coupling_on = true;
   g_last_error.clear();
   return GMM_OK;
 }

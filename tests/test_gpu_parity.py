@@ -430,3 +430,78 @@ def test_gain_saturates_logistically_on_gpu(torch_gpu):
     got = float(np.sum(np.abs(A) ** 2) * dt)
     print(f"logistic energy {got:.6e} expected {expect:.6e}", flush=True)
     assert abs(got / expect - 1) < 1e-9
+
+
+def _coupling(w, seed=6, scale=50.0, complex_values=True):
+    rng = np.random.default_rng(synth.SEED_BASE + 5000 + seed)
+    Q = rng.standard_normal((w.n_modes, w.n_modes)) * scale
+    if complex_values:
+        Q = Q + 1j * rng.standard_normal((w.n_modes, w.n_modes)) * scale
+    return Q
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", [(2, 256, 0.0, 1, False), (3, 1024, 0.18, 0, True), (5, 1024, 0.18, 0, True)],
+                         ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_policy{c[3]}_gain{int(c[4])}")
+def test_coupling_operator_matches_oracle(torch_gpu, prec, case):
+    """Linear mode coupling (complex Q) added to the operator, alone or with the
+    saturating gain, through the packed and rank-r routes, against the oracle."""
+    torch = torch_gpu
+    g_, nt, fR, policy, with_gain = case
+    w = small_workload(N_groups=g_, nt=nt, fR=fR, s=1, dt=20480e-15 / nt)
+    Q = _coupling(w)
+    m = O.model_from_workload(w)
+    m.Q = Q
+    plan = make_plan(w, prec, factor_policy=policy)
+    plan.set_coupling(Q)
+    if with_gain:
+        g, I_sat = _gain_setup(w)
+        m.gain, m.I_sat = g, I_sat
+        plan.set_gain(g, I_sat)
+    ops = O._Ops(m, w.nt)
+    spectra = [O.to_spectrum(w.A0 * (1 + 0.5 * c)) for c in range(2)]
+    ref = np.stack([ops.N(a) for a in spectra])
+    got = plan.nonlinear(to_dev(torch, np.stack(spectra), prec)).cpu().numpy()
+    err = relmax(got, ref)
+    print(f"[{prec} {case}] coupling operator error {err:.3e}", flush=True)
+    assert err < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_coupling_propagation_matches_oracle(torch_gpu, prec):
+    """6 modes with Raman, shock and a real symmetric coupling matrix: MPA (fixed
+    iterations) and RK4IP against the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=512, fR=0.18, s=1, dt=40e-15)
+    Qr = _coupling(w, complex_values=False, scale=200.0)
+    Q = Qr + Qr.T
+    m = O.model_from_workload(w)
+    m.Q = Q
+    L = 7 * w.dz
+    ref_mpa = O.mpa_propagate(w.A0, m, L, w.dz, 3, fixed_iters=4)
+    ref_rk = O.rk4ip_propagate(w.A0, m, L, w.dz)
+    plan = make_plan(w, prec, fixed_iters=4)
+    plan.set_coupling(Q)
+    e1 = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 3).field.cpu().numpy(), ref_mpa)
+    e2 = relmax(plan.propagate_rk4ip(to_dev(torch, w.A0, prec), L, w.dz).field.cpu().numpy(), ref_rk)
+    print(f"[{prec}] coupling MPA {e1:.3e} RK4IP {e2:.3e}", flush=True)
+    assert e1 < TOL_PROP[prec] and e2 < TOL_PROP[prec]
+
+
+def test_two_mode_coupler_on_gpu(torch_gpu):
+    """Two modes, Q = [[0, k], [k, 0]], mismatch db0 = d, no Kerr: the GPU RK4IP
+    moves (k / W)^2 sin^2(W L) of the power, W = sqrt(k^2 + (d/2)^2)."""
+    torch = torch_gpu
+    from paper_1708_05324_amd import gmmpa
+    nt, dt, k, d, L = 256, 50e-15, 30.0, 40.0, 0.05
+    t = synth.time_grid(nt, dt)
+    A0 = np.stack([np.exp(-t ** 2 / (2 * (500e-15) ** 2)) + 0j, np.zeros(nt, complex)])
+    betas = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    plan = gmmpa.Plan(betas, np.zeros((2, 2, 2, 2)), None, nt=nt, dt=dt, omega0=synth.GrinFiber().omega0,
+                      n2=0.0, fR=0.0, self_steepening=0, precision="fp64")
+    plan.set_coupling(np.array([[0.0, k], [k, 0.0]]))
+    A = plan.propagate_rk4ip(to_dev(torch, A0, "fp64"), L, L / 500).field.cpu().numpy()
+    W = math.sqrt(k ** 2 + (d / 2) ** 2)
+    frac = float(np.sum(np.abs(A[1]) ** 2) / np.sum(np.abs(A0) ** 2))
+    print(f"coupler fraction {frac:.10f} expected {(k / W) ** 2 * math.sin(W * L) ** 2:.10f}", flush=True)
+    assert abs(frac - (k / W) ** 2 * math.sin(W * L) ** 2) < 1e-10
