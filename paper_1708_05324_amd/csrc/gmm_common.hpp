@@ -20,6 +20,8 @@ struct Ctrl {
 // and the samples per partial sum of the pair integrals.
 constexpr int kGainNmax = 22;
 constexpr int kGainChunkHost = 128;
+// Partial sums per sub-step of the pair integrals: 64 (or Nt / 128 for short windows).
+inline int gain_partials(int nt) { return nt / kGainChunkHost < 64 ? nt / kGainChunkHost : 64; }
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cplx {

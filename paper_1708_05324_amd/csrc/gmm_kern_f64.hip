@@ -63,8 +63,10 @@ hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, do
 // k_gain_matrix: the per-sub-step matrix of the linear-in-A terms of Sec. III.F,
 //   Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn)   (g != nullptr)
 //         + K_pl                                                (K != nullptr)
-// with Phi = dt * (sum of the chunk partials, fixed order) and K_pl = i Q_lp
-// the linear mode coupling.  grid (count).
+// with Phi = dt * (sum of the C partials, fixed order) and K_pl = i Q_lp the
+// linear mode coupling.  grid (N, count): block (p, j) forms row p; wave w
+// takes l = w, w + 4, ..., its lanes split the (m, n) sum, and a fixed-order
+// shuffle reduction closes it.
 __global__ __launch_bounds__(256) void k_gain_matrix(const cplx<double>* __restrict__ part, int C,
                                                      const cplx<double>* __restrict__ SR,
                                                      const double* __restrict__ g, double inv_Isat, double dt,
@@ -72,8 +74,10 @@ __global__ __launch_bounds__(256) void k_gain_matrix(const cplx<double>* __restr
                                                      cplx<double>* __restrict__ Mg, int N, const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
   __shared__ cplx<double> sPhi[kGainNmax * kGainNmax];
-  const int tid = threadIdx.x, jj = blockIdx.x, NN = N * N;
-  if (g != nullptr && inv_Isat != 0.0) {
+  const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, NN = N * N;
+  const int lane = tid & 63, wave = tid >> 6;
+  const bool sat = g != nullptr && inv_Isat != 0.0;
+  if (sat) {
     for (int q = tid; q < NN; q += 256) {
       double re = 0.0, im = 0.0;
       for (int c = 0; c < C; ++c) {
@@ -85,24 +89,30 @@ __global__ __launch_bounds__(256) void k_gain_matrix(const cplx<double>* __restr
     }
   }
   __syncthreads();
-  for (int q = tid; q < NN; q += 256) {
-    const int p = q / N, l = q - p * N;
-    cplx<double> m = K != nullptr ? K[q] : cplx<double>{0.0, 0.0};
-    if (g != nullptr) {
-      double re = 0.0, im = 0.0;
-      if (inv_Isat != 0.0) {
-        const cplx<double>* srow = SR + (size_t)q * NN;   // S^R_plmn, (m, n) contiguous
-        for (int mn = 0; mn < NN; ++mn) {
-          const cplx<double> a = srow[mn], b = sPhi[mn];
-          re += a.re * b.re - a.im * b.im;
-          im += a.re * b.im + a.im * b.re;
-        }
+  for (int l = wave; l < N; l += 4) {
+    double re = 0.0, im = 0.0;
+    if (sat) {
+      const cplx<double>* srow = SR + ((size_t)p * N + l) * NN;   // S^R_plmn, (m, n) contiguous
+      for (int mn = lane; mn < NN; mn += 64) {
+        const cplx<double> a = srow[mn], b = sPhi[mn];
+        re += a.re * b.re - a.im * b.im;
+        im += a.re * b.im + a.im * b.re;
       }
-      const double d = p == l ? 1.0 : 0.0;
-      m.re += g[p] * (d - inv_Isat * re);
-      m.im -= g[p] * inv_Isat * im;
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+      }
     }
-    Mg[(size_t)jj * NN + q] = m;
+    if (lane == 0) {
+      const int q = p * N + l;
+      cplx<double> m = K != nullptr ? K[q] : cplx<double>{0.0, 0.0};
+      if (g != nullptr) {
+        const double d = p == l ? 1.0 : 0.0;
+        m.re += g[p] * (d - inv_Isat * re);
+        m.im -= g[p] * inv_Isat * im;
+      }
+      Mg[(size_t)jj * NN + q] = m;
+    }
   }
 }
 
@@ -110,7 +120,7 @@ hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double
                               double inv_Isat, double dt, const cplx<double>* K, cplx<double>* Mg, int N, int count,
                               const Ctrl* ctrl, hipStream_t s) {
   if (N > kGainNmax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gain_matrix, dim3(count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, K, Mg, N, ctrl);
+  hipLaunchKernelGGL(k_gain_matrix, dim3(N, count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, K, Mg, N, ctrl);
   return hipGetLastError();
 }
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s) {

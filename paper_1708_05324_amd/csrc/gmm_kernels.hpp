@@ -1294,32 +1294,51 @@ __global__ __launch_bounds__(256) void k_rk4ip_stage(int stage, cplx<T>* __restr
 // G is linear in A with a time-independent matrix, so it is applied to the
 // spectra: I_j += exp(-D_w z_j) Mg (exp(D_w z_j) psi_j).
 //
-// k_pair_integrals: partial sums of A_m(t) A_n^*(t) over 128-sample chunks, in
-// FP64.  grid (Nt / 128, count); the chunk's fields are staged in LDS and each
-// thread sums whole (m, n) entries.  Out: [count][chunks][N][N] complex.
+// k_pair_integrals: partial sums of A_m(t) A_n^*(t) over 1/C of the window per
+// block, in FP64.  grid (C, count); the block walks its range in tiles of 128
+// samples staged in LDS sample-major (the lanes of a wave read neighbouring
+// modes of one sample: no bank conflicts), each thread summing whole (m, n)
+// entries.  Out: [count][C][N][N] complex.
 constexpr int kGainChunk = kGainChunkHost;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pair_integrals(const cplx<T>* __restrict__ A, cplx<double>* __restrict__ part,
                                                         int N, int Nt, const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
-  __shared__ cplx<T> sA[kGainNmax * kGainChunk];
+  __shared__ cplx<T> sA[kGainChunk * kGainNmax];
   const int tid = threadIdx.x, c = blockIdx.x, jj = blockIdx.y, C = gridDim.x;
-  const cplx<T>* Aj = A + (size_t)jj * N * Nt + (size_t)c * kGainChunk;
-  for (int i = tid; i < N * kGainChunk; i += 256) {
-    const int l = i / kGainChunk, t = i - l * kGainChunk;
-    sA[i] = Aj[(size_t)l * Nt + t];
-  }
-  __syncthreads();
-  for (int q = tid; q < N * N; q += 256) {
-    const int m = q / N, n = q - m * N;
-    double re = 0.0, im = 0.0;
-    for (int t = 0; t < kGainChunk; ++t) {
-      const cplx<T> a = sA[m * kGainChunk + t], b = sA[n * kGainChunk + t];
-      re += (double)a.re * b.re + (double)a.im * b.im;
-      im += (double)a.im * b.re - (double)a.re * b.im;
+  const int span = Nt / C;  // a multiple of kGainChunk
+  const cplx<T>* Aj = A + (size_t)jj * N * Nt + (size_t)c * span;
+  const int NN = N * N;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  // entries q = tid and tid + 256 (N <= 22: NN <= 484)
+  for (int t0 = 0; t0 < span; t0 += kGainChunk) {
+    __syncthreads();
+    for (int i = tid; i < N * kGainChunk; i += 256) {
+      const int l = i / kGainChunk, t = i - l * kGainChunk;
+      sA[t * N + l] = Aj[(size_t)l * Nt + t0 + t];
     }
-    part[(((size_t)jj * C + c) * N + m) * N + n] = cplx<double>{re, im};
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NN) {
+        const int m = q / N, n = q - m * N;
+        double re[4] = {0.0, 0.0, 0.0, 0.0}, im[4] = {0.0, 0.0, 0.0, 0.0};  // four chains for ILP
+#pragma unroll 8
+        for (int t = 0; t < kGainChunk; ++t) {
+          const cplx<T> x = sA[t * N + m], y = sA[t * N + n];
+          re[t & 3] += (double)x.re * y.re + (double)x.im * y.im;
+          im[t & 3] += (double)x.im * y.re - (double)x.re * y.im;
+        }
+        acc[r][0] += (re[0] + re[1]) + (re[2] + re[3]);
+        acc[r][1] += (im[0] + im[1]) + (im[2] + im[3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = tid + 256 * r;
+    if (q < NN) part[((size_t)jj * C + c) * NN + q] = cplx<double>{acc[r][0], acc[r][1]};
   }
 }
 
@@ -1338,25 +1357,26 @@ __global__ __launch_bounds__(256) void k_gain_add(const cplx<T>* __restrict__ ps
     sM[q] = cplx<T>{(T)v.re, (T)v.im};
   }
   __syncthreads();
-  cplx<T> a[kGainNmax];
+  cplx<T> a[kGainNmax], e[kGainNmax];
 #pragma unroll
   for (int l = 0; l < kGainNmax; ++l) {
     if (l < N) {
       const cplx<T> x = psi[((size_t)jj * psi_jrows + l) * Nt + k];
-      a[l] = E != nullptr ? cmul(E[((size_t)(j0 + jj) * N + l) * Nt + k], x) : x;
+      e[l] = E != nullptr ? E[((size_t)(j0 + jj) * N + l) * Nt + k] : cplx<T>{T(1), T(0)};
+      a[l] = cmul(e[l], x);
     }
   }
-  for (int p = 0; p < N; ++p) {
-    cplx<T> gsum = {T(0), T(0)};
 #pragma unroll
-    for (int l = 0; l < kGainNmax; ++l)
-      if (l < N) gsum = cadd(gsum, cmul(sM[p * N + l], a[l]));
-    if (E != nullptr) {
-      const cplx<T> e = E[((size_t)(j0 + jj) * N + p) * Nt + k];
-      gsum = cmul(gsum, cplx<T>{e.re, -e.im});
+  for (int p = 0; p < kGainNmax; ++p) {
+    if (p < N) {
+      cplx<T> gsum = {T(0), T(0)};
+#pragma unroll
+      for (int l = 0; l < kGainNmax; ++l)
+        if (l < N) gsum = cadd(gsum, cmul(sM[p * N + l], a[l]));
+      gsum = cmul(gsum, cplx<T>{e[p].re, -e[p].im});
+      cplx<T>& o = out[((size_t)jj * N + p) * Nt + k];
+      o = cadd(o, gsum);
     }
-    cplx<T>& o = out[((size_t)jj * N + p) * Nt + k];
-    o = cadd(o, gsum);
   }
 }
 

@@ -248,7 +248,7 @@ template <typename T>
 hipError_t Launch<T>::pair_integrals(const cplx<T>* A, cplx<double>* part, int N, int Nt, int count,
                                      const Ctrl* ctrl, hipStream_t s) {
   if (N > kGainNmax || Nt % kGainChunk) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_pair_integrals<T>), dim3(Nt / kGainChunk, count), dim3(256), 0, s, A, part, N, Nt, ctrl);
+  hipLaunchKernelGGL((k_pair_integrals<T>), dim3(gain_partials(Nt), count), dim3(256), 0, s, A, part, N, Nt, ctrl);
   return hipGetLastError();
 }
 

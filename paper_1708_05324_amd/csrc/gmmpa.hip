@@ -228,7 +228,7 @@ int ensure_gain_workspace(gmm_plan_s* P, int cap) {
   const size_t nn = (size_t)P->N * P->N;
   void* a = nullptr;
   void* b = nullptr;
-  if (hipMalloc(&a, (size_t)cap * (P->nt / gmm::kGainChunkHost) * nn * sizeof(cplx<double>)) != hipSuccess ||
+  if (hipMalloc(&a, (size_t)cap * gmm::gain_partials(P->nt) * nn * sizeof(cplx<double>)) != hipSuccess ||
       hipMalloc(&b, (size_t)cap * nn * sizeof(cplx<double>)) != hipSuccess) {
     (void)hipGetLastError();
     if (a) (void)hipFree(a);
@@ -300,7 +300,7 @@ struct Runner {
       if (P->gain_on && P->inv_Isat != 0.0)
         GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
       GMM_LAUNCH(P, GMM_PROF_GAIN,
-                 gmm::launch_gain_matrix(P->gpart, P->nt / gmm::kGainChunkHost, P->SRd,
+                 gmm::launch_gain_matrix(P->gpart, gmm::gain_partials(P->nt), P->SRd,
                                          P->gain_on ? P->gvec : nullptr, P->inv_Isat, P->prm.dt,
                                          P->coupling_on ? P->Kc : nullptr, P->Mg, P->N, count, ctrl, P->stream));
     }
