@@ -600,7 +600,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
 // the waves never wait for each other.
 //   BF16: U and Y' as hi/lo planes; v_mfma_f32_16x16x32_bf16, products
 //         hi*hi + hi*lo + lo*hi, FP32 accumulation.  Y' planes of words
-//         [count][32][Nt] (word i holds rows 2i and 2i + 1).
+//         [count][32][Nt] (word i holds rows 2i and 2i + 1), kv valid rows.
 //   FP32: v_mfma_f32_16x16x4f32.  Y' [count][kv][Nt], rows clamped to kv - 1
 //         (U is zero there).
 __host__ __device__ constexpr int tri_mode_l(int Q) {
@@ -676,9 +676,11 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
     bf16x8 yh[BF16 ? 4 : 1][2], yl[BF16 ? 4 : 1][2];
     float yf[BF16 ? 1 : 4][BF16 ? 1 : 16];
     if constexpr (BF16) {
-      // word (i, t) of a plane holds rows 2i, 2i + 1: the eight rows 32 ks + 8 lk .. + 7 are words 16 ks + 4 lk + e
+      // word (i, t) of a plane holds rows 2i, 2i + 1: the eight rows 32 ks + 8 lk .. + 7 are words 16 ks + 4 lk + e;
+      // words at or beyond the kv valid rows are zero and are not read
       const uint32_t* ph = reinterpret_cast<const uint32_t*>(Ya) + (size_t)jj * 32 * Nt + t0 + lr;
       const uint32_t* pl = reinterpret_cast<const uint32_t*>(Yb) + (size_t)jj * 32 * Nt + t0 + lr;
+      const int kw = (kv + 1) >> 1;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -686,9 +688,10 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
           uint32_t wh[4], wl[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const size_t o = (size_t)(16 * ks + 4 * lk + e) * Nt + cb * 16;
-            wh[e] = ph[o];
-            wl[e] = pl[o];
+            const int word = 16 * ks + 4 * lk + e;
+            const size_t o = (size_t)word * Nt + cb * 16;
+            wh[e] = word < kw ? ph[o] : 0u;
+            wl[e] = word < kw ? pl[o] : 0u;
           }
           yh[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wh[0], wh[1], wh[2], wh[3]});
           yl[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wl[0], wl[1], wl[2], wl[3]});

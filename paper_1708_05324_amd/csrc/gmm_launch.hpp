@@ -64,8 +64,8 @@ hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* S
                                 const uint32_t* Blo, cplx<float>* A_NL, const int* pidx, int N, int Nt, int count,
                                 const Ctrl* ctrl, hipStream_t s);
 // Column-owner contraction of the rank-r route (complex64 fields, Rpad 64 or 128,
-// K = 64): BF16 split (Ua/Ub = U hi/lo [Rpad][64] bf16, Ya/Yb = Y' planes) or
-// FP32 (Ua = U^T [64][Rpad], Ya = Y' [count][kv][Nt]).
+// K = 64): BF16 split (Ua/Ub = U hi/lo [Rpad][64] bf16, Ya/Yb = Y' planes of
+// 2-row words, kv valid rows) or FP32 (Ua = U^T [64][Rpad], Ya = Y' [count][kv][Nt]).
 hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
                                 cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
                                 hipStream_t s);

@@ -328,7 +328,7 @@ struct Runner {
           GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
                                                               (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
-                                                                     P->N, P->rq, P->nt, count, ctrl, P->stream));
+                                                                     P->N, R, P->nt, count, ctrl, P->stream));
         }
       }
       if (!P->bf16) {

@@ -505,3 +505,40 @@ def test_two_mode_coupler_on_gpu(torch_gpu):
     frac = float(np.sum(np.abs(A[1]) ** 2) / np.sum(np.abs(A0) ** 2))
     print(f"coupler fraction {frac:.10f} expected {(k / W) ** 2 * math.sin(W * L) ** 2:.10f}", flush=True)
     assert abs(frac - (k / W) ** 2 * math.sin(W * L) ** 2) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_general_route_21_modes_with_gain(torch_gpu, prec):
+    """21 modes (the largest group count in this build): general route with a
+    complex S^K != S^R (882 output rows, K = 924; the FP64 tile needs more than
+    64 KB of LDS) plus the saturating gain, against the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=6, nt=256, fR=0.18, s=1, dt=80e-15)
+    m, SK, SR = _general_model(w, True, True, seed=9)
+    g, I_sat = _gain_setup(w)
+    m.gain, m.I_sat = g, I_sat
+    ops = O._Ops(m, w.nt)
+    At = O.to_spectrum(w.A0)[None]
+    plan = _general_plan(w, SK, SR, prec)
+    plan.set_gain(g, I_sat)
+    err = relmax(plan.nonlinear(to_dev(torch, At, prec)).cpu().numpy(), ops.N(At[0])[None])
+    print(f"[{prec}] 21-mode general route + gain error {err:.3e}", flush=True)
+    assert err < TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_longest_window_2_to_15(torch_gpu, prec):
+    """Nt = 2^15 (the longest FP32 row: 32 points per thread, 1024 threads):
+    operator of a 3-mode Kerr + Raman + shock plan and one large step, against
+    the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=2, nt=2 ** 15, fR=0.18, s=1, dt=2.5e-15)
+    m = O.model_from_workload(w)
+    ops = O._Ops(m, w.nt)
+    At = O.to_spectrum(w.A0)[None]
+    plan = make_plan(w, prec, fixed_iters=3)
+    e1 = relmax(plan.nonlinear(to_dev(torch, At, prec)).cpu().numpy(), ops.N(At[0])[None])
+    ref = O.mpa_propagate(w.A0, m, 5 * w.dz, w.dz, 5, fixed_iters=3)
+    e2 = relmax(plan.propagate(to_dev(torch, w.A0, prec), 5 * w.dz, w.dz, 5).field.cpu().numpy(), ref)
+    print(f"[{prec}] 2^15 operator {e1:.3e} propagation {e2:.3e}", flush=True)
+    assert e1 < TOL_OP[prec] and e2 < TOL_PROP[prec]
