@@ -284,7 +284,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard).", file=sys.stderr)
+              "(the sub-step split of one large step is how it would shard).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -2,9 +2,10 @@
 
 Error measure: max |A - A_ref| / max |A_ref| over all modes and samples (the
 field error normalised by the global peak).  Tolerances: FP64 paths 1e-11
-(operator) / 1e-10 (propagation); FP32 paths 2e-5 / 1e-5.  The FP32 bound is
-the spec field tolerance; the operator bound allows the sum over up to
-Np^2 terms in FP32 (about Np * 2^-24 * max term).
+(operator) / 1e-10 (propagation); FP32 paths 2e-5 / 1e-5; BF16 split 1e-4 /
+1e-3.  The propagation bounds are the stated field tolerances of the FP32 and
+BF16-split paths; the operator bound allows the sum over up to Np^2 terms in
+FP32 (about Np * 2^-24 * max term).
 """
 import math
 
