@@ -345,7 +345,7 @@ def main():
         scale = float(w.S[0, 0, 0, 0])
         SK = synth.random_general_tensor(0, w.n_modes) * scale
         SR = synth.random_general_tensor(1, w.n_modes) * scale
-        prec = "fp32" if args.precision == "bf16x3" else args.precision
+        prec = args.precision
 
         def make(p):
             return gmmpa.Plan(w.betas, SK, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,

@@ -161,7 +161,10 @@ struct gmm_plan_s {
   // general-tensor route (S^R != S^K, complex S, or S without the packed symmetries)
   bool dense = false;
   int KD = 0, rows_pad = 0;  // real pair rows per sub-step (multiple of 4); output rows 2 N^2 padded to 64
+  int KD32 = 0;              // KD rounded up to 32 (BF16 split operand)
   void* G = nullptr;         // [rows_pad][KD] real coupling matrix of the general route, field precision
+  void* Ghi = nullptr;       // [rows_pad][KD32] bf16 split of G (BF16X3 plans)
+  void* Glo = nullptr;
   // saturating gain (Sec. III.F): G = Mg A per sub-step
   std::vector<std::complex<double>> SRh;  // host copy of S^R (S^K when SR is NULL), [N^4]
   bool gain_on = false;
@@ -308,8 +311,18 @@ struct Runner {
       GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
                                                            count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
                                                            P->stream));
-      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)P->Bp, W, P->N, P->KD,
-                                                                 P->rows_pad, P->nt, count, ctrl, P->stream));
+      bool done = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (P->bf16) {
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT,
+                     gmm::launch_contract_dense_bf16(P->Ghi, P->Glo, (const float*)P->Bp, W, P->N, P->KD, P->KD32,
+                                                     P->rows_pad, P->nt, count, ctrl, P->stream));
+          done = true;
+        }
+      }
+      if (!done)
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)P->Bp, W, P->N, P->KD,
+                                                                   P->rows_pad, P->nt, count, ctrl, P->stream));
     } else if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
       T* Y = (T*)P->Y;
       if constexpr (std::is_same<T, float>::value) {
@@ -786,6 +799,22 @@ int upload_dense(gmm_plan_s* P, FK sk, FR sr) {
   int rc;
   if ((rc = dev_alloc(&P->const_bytes, &P->G, g.size() * sizeof(T)))) return rc;
   GMM_HIP(hipMemcpy(P->G, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice));
+  P->KD32 = (P->KD + 31) / 32 * 32;
+  if (P->bf16) {  // hi/lo split of G for the BF16X3 product, K padded to 32 with zeros
+    std::vector<uint16_t> hi((size_t)P->rows_pad * P->KD32, 0), lo((size_t)P->rows_pad * P->KD32, 0);
+    for (int r = 0; r < P->rows_pad; ++r)
+      for (int k = 0; k < P->KD; ++k) {
+        const float x = (float)g[(size_t)r * P->KD + k];
+        const uint16_t h = host_bf16(x);
+        hi[(size_t)r * P->KD32 + k] = h;
+        lo[(size_t)r * P->KD32 + k] = host_bf16(x - host_bf16_value(h));
+      }
+    if ((rc = dev_alloc(&P->const_bytes, &P->Ghi, hi.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Glo, lo.size() * 2)))
+      return rc;
+    GMM_HIP(hipMemcpy(P->Ghi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Glo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
+  }
   return GMM_OK;
 }
 
@@ -817,7 +846,7 @@ void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
-                  P->G, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
+                  P->G, P->Ghi, P->Glo, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
                   (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
