@@ -143,150 +143,225 @@ hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, cons
 // ([rows_pad][KD32], K padded with zeros); B is split on the fly from the FP32
 // pair rows; products hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16.
 //
-// One block of 8 waves owns 128 columns; wave w owns columns 16 w .. 16 w + 15
-// and every output row, so its accumulators (32 blocks of 16 x 16) stay in
-// registers for the whole K loop and B is read once.  Each 32-wide K slice of G
-// (hi and lo, all rows) is staged in LDS once per block and read by all eight
-// waves: G leaves L2 once per 128 columns.  The 16-byte chunks of a G row are
-// XOR-swizzled by bits 1-2 of the row so that eight consecutive lanes of a
-// 128-bit LDS read hit distinct banks.  After the K loop the accumulators pass
-// through LDS in pieces of 64 rows and are folded into NL (thread (t, g) owns
-// the modes p = g mod 4, fixed summation order).  NL overwrites A.
-constexpr int kDenseCols = 128, kDenseRB = 29;
-constexpr size_t kDenseSlice = (size_t)kDenseRB * 16 * 64;  // bytes of one plane (hi or lo) of one K slice
-constexpr size_t kDenseGBytes = 4 * kDenseSlice;              // two slices (double buffer), hi and lo each
+// One block of 4 waves owns 128 columns; wave w owns columns 32 w .. 32 w + 31
+// (two blocks of 16) and every output row, so its accumulators (2 x 29 tiles of
+// 16 x 16) stay in registers for the whole K loop and B is read once.  Each
+// 32-wide K slice of G (hi and lo, all rows) is copied straight from global
+// memory into LDS once per block (double-buffered: the next slice is in flight
+// during the products) and every fragment read from LDS feeds both column
+// blocks.  The 16-byte
+// chunks of a G row are XOR-swizzled by bits 1-2 of the row so that eight
+// consecutive lanes of a 128-bit LDS read hit distinct banks.  After the K loop
+// the accumulators pass through LDS in pieces of 64 rows (32 pairs pl) and are
+// folded into NL: thread (t, g) sums C_pl A_l over pairs 16 g .. 16 g + 15 of
+// each piece in registers and adds each mode's partial to its own NL partial
+// (fixed summation order, no atomics); NL = partial 0 + partial 1 overwrites A.
+//
+// Cost at 15 modes (2^14 samples, 128 columns a block): the products, the
+// fragment reads from LDS, the G slices out of L2 and the fold take comparable
+// shares; one wave per SIMD (232 accumulator registers) leaves little latency
+// hiding.
+constexpr int kDenseCols = 128, kDenseRB = 29, kDenseThreads = 256;  // kDenseRB: row blocks at 15 modes
+constexpr size_t kDenseSlice = (size_t)kDenseRB * 16 * 64;    // bytes of one plane (hi or lo) of one K slice
+constexpr size_t kDenseGBytes = 4 * kDenseSlice;                // two slices (double buffer), hi and lo each
+static_assert(kDenseRB * 16 == kDenseGRows, "G hi/lo rows as allocated by the plan");
+constexpr int kDenseCS = kDenseCols + 4;                         // row stride of a C piece (floats)
+constexpr int kDenseAR = (15 * kDenseCols + kDenseThreads - 1) / kDenseThreads;  // A elements per thread
+constexpr size_t kDenseFoldA = (size_t)64 * kDenseCS * sizeof(float);           // A tile offset in the fold
+static_assert(kDenseFoldA + (size_t)3 * 15 * kDenseCols * sizeof(cplx<float>) <= kDenseGBytes,
+              "the fold buffers fit in the G region");
 
-__global__ __launch_bounds__(512) void k_contract_dense_bf16(const uint4* __restrict__ Ghi,
-                                                             const uint4* __restrict__ Glo,
-                                                             const float* __restrict__ Bd, cplx<float>* A_NL, int N,
-                                                             int KD, int KD32, int nrb, int Nt, const Ctrl* ctrl) {
+template <int NRB>  // row blocks of 16 computed (the rows beyond 2 N^2 are zero in G)
+__global__ __launch_bounds__(kDenseThreads) void k_contract_dense_bf16(const uint4* __restrict__ Ghi,
+                                                                       const uint4* __restrict__ Glo,
+                                                                       const float* __restrict__ Bd,
+                                                                       cplx<float>* A_NL, int N, int KD, int KD32,
+                                                                       int Nt, const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // K loop: the G slices.  Fold: C piece [64][kDenseCS], A tile [N][128], two NL partials [N][128] (one per
+  // half of each piece's pairs), all inside the G region once the K loop is over.
   unsigned char* sG = smem_raw;                                          // [2 slices][hi, lo][kDenseRB * 16][64 B]
-  float* sC = reinterpret_cast<float*>(smem_raw);                        // [64][128], aliases sG after the K loop
-  cplx<float>* sA = reinterpret_cast<cplx<float>*>(smem_raw + kDenseGBytes);  // [N][128]
-  cplx<float>* sNL = sA + N * kDenseCols;                                // [N][128]
+  float* sC = reinterpret_cast<float*>(smem_raw);
+  cplx<float>* sA = reinterpret_cast<cplx<float>*>(smem_raw + kDenseFoldA);
+  cplx<float>* sNL0 = sA + N * kDenseCols;
+  cplx<float>* sNL1 = sNL0 + N * kDenseCols;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int tiles_per_j = Nt / kDenseCols;
   const int jj = blockIdx.x / tiles_per_j, t0 = (blockIdx.x - jj * tiles_per_j) * kDenseCols;
   cplx<float>* Aj = A_NL + (size_t)jj * N * Nt + t0;
-  const float* Bj = Bd + (size_t)jj * KD * Nt + t0 + 16 * wave + lr;
-  for (int i = tid; i < N * kDenseCols; i += 512) {
-    sA[i] = Aj[(size_t)(i >> 7) * Nt + (i & 127)];
-    sNL[i] = cplx<float>{0.f, 0.f};
-  }
-  const int KC = KD32 / 8;            // 16-byte chunks per G row
-  const int nitems = nrb * 16 * 8;    // (row, chunk) items of one K slice: 4 hi + 4 lo chunks per row
-  // fill item it = tid + 512 i: row = it >> 3, plane (hi 0, lo 1) = (it >> 2) & 1, chunk c = it & 3; the
-  // thread's global offset and LDS offset are the same for every slice (plus 4 ks chunks, plus the slice)
-  const uint4* gsrc[8];
-  int gdst[8];
+  const float* Bj = Bd + (size_t)jj * KD * Nt + t0 + 32 * wave + lr;
+  cplx<float> areg[kDenseAR];  // this thread's share of the A tile, held through the K loop
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int it = min(tid + 512 * i, nitems - 1), row = it >> 3, c = it & 3, plane = (it >> 2) & 1;
-    gsrc[i] = (plane ? Glo : Ghi) + (size_t)row * KC + c;
-    gdst[i] = tid + 512 * i < nitems ? plane * (int)kDenseSlice + row * 64 + ((c ^ (row >> 1)) & 3) * 16 : -1;
+  for (int r = 0; r < kDenseAR; ++r) {
+    const int i = tid + kDenseThreads * r;
+    if (i < N * kDenseCols) areg[r] = Aj[(size_t)(i >> 7) * Nt + (i & 127)];
   }
-  floatx4 acc[kDenseRB];
+  // staging of a K slice: straight from global memory into LDS (global_load_lds_dwordx4: lane i of a wave
+  // writes bytes 16 i .. 16 i + 15 of a 1 KB LDS block).  Unit u = 2 rb + plane (hi 0, lo 1) is rows
+  // 16 rb .. 16 rb + 15 of one plane; lane i fills row 16 rb + i / 4 at swizzled position i % 4, i.e. it
+  // loads chunk (i % 4) ^ ((row >> 1) % 4) = (i % 4) ^ ((i / 8) % 4) of that row.
+  const int KC = KD32 / 8;  // 16-byte chunks per G row
+  constexpr int nunits = 2 * NRB;
+  const size_t lane_src = (size_t)(lane >> 2) * KC + ((lane & 3) ^ ((lane >> 3) & 3));
+  auto stage = [&](int ks, int buf) {
+    for (int u = wave; u < nunits; u += 4) {
+      const int rb = u >> 1, plane = u & 1;
+      const uint4* src = (plane ? Glo : Ghi) + (size_t)16 * rb * KC + 4 * ks + lane_src;
+      unsigned char* dst = sG + (size_t)buf * 2 * kDenseSlice + (size_t)plane * kDenseSlice + (size_t)rb * 1024;
+      __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+  floatx4 acc0[NRB], acc1[NRB];
 #pragma unroll
-  for (int rb = 0; rb < kDenseRB; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  uint4 g0, g1, g2, g3, g4, g5, g6, g7;
-  float x[8];
-#define GMM_DENSE_LOAD(ks)                                                                          \
-  g0 = gsrc[0][4 * (ks)]; g1 = gsrc[1][4 * (ks)]; g2 = gsrc[2][4 * (ks)]; g3 = gsrc[3][4 * (ks)];   \
-  g4 = gsrc[4][4 * (ks)]; g5 = gsrc[5][4 * (ks)]; g6 = gsrc[6][4 * (ks)]; g7 = gsrc[7][4 * (ks)];
-#define GMM_DENSE_STORE(buf)                                                                        \
-  {                                                                                                 \
-    unsigned char* d = sG + (buf) * 2 * kDenseSlice;                                                \
-    const uint4 gv[8] = {g0, g1, g2, g3, g4, g5, g6, g7};                                          \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) if (gdst[i] >= 0)                                 \
-        *reinterpret_cast<uint4*>(d + gdst[i]) = gv[i];                                            \
-  }
+  for (int rb = 0; rb < NRB; ++rb) acc0[rb] = acc1[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float x0[8], x1[8];
   const int nks = KD32 / 32;
-  GMM_DENSE_LOAD(0);
+  stage(0, 0);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) x[e] = 8 * lk + e < KD ? Bj[(size_t)(8 * lk + e) * Nt] : 0.f;
-  GMM_DENSE_STORE(0);
+  for (int e = 0; e < 8; ++e) {
+    const int k = 8 * lk + e;
+    x0[e] = k < KD ? Bj[(size_t)k * Nt] : 0.f;
+    x1[e] = k < KD ? Bj[(size_t)k * Nt + 16] : 0.f;
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's LDS fills have landed
   __syncthreads();
   const int swz = ((lk ^ (lr >> 1)) & 3) * 16;  // swizzled chunk lk of row 16 rb + lr
   for (int ks = 0; ks < nks; ++ks) {
     uint32_t h[4], l[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bf16_split2(x[2 * e], x[2 * e + 1], h[e], l[e]);
-    const bf16x8 bh = __builtin_bit_cast(bf16x8, uint4{h[0], h[1], h[2], h[3]});
-    const bf16x8 bl = __builtin_bit_cast(bf16x8, uint4{l[0], l[1], l[2], l[3]});
-    if (ks + 1 < nks) {  // next slice of G and of B in flight during this slice's products
-      GMM_DENSE_LOAD(ks + 1);
+    for (int e = 0; e < 4; ++e) bf16_split2(x0[2 * e], x0[2 * e + 1], h[e], l[e]);
+    const bf16x8 bh0 = __builtin_bit_cast(bf16x8, uint4{h[0], h[1], h[2], h[3]});
+    const bf16x8 bl0 = __builtin_bit_cast(bf16x8, uint4{l[0], l[1], l[2], l[3]});
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bf16_split2(x1[2 * e], x1[2 * e + 1], h[e], l[e]);
+    const bf16x8 bh1 = __builtin_bit_cast(bf16x8, uint4{h[0], h[1], h[2], h[3]});
+    const bf16x8 bl1 = __builtin_bit_cast(bf16x8, uint4{l[0], l[1], l[2], l[3]});
+    if (ks + 1 < nks) {  // next slice of G (into the other buffer, last read before the previous barrier)
+      stage(ks + 1, (ks + 1) & 1);  // and of B in flight during this slice's products
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 32 * (ks + 1) + 8 * lk + e;
-        x[e] = k < KD ? Bj[(size_t)k * Nt] : 0.f;
+        x0[e] = k < KD ? Bj[(size_t)k * Nt] : 0.f;
+        x1[e] = k < KD ? Bj[(size_t)k * Nt + 16] : 0.f;
       }
     }
     const unsigned char* src = sG + (ks & 1) * 2 * kDenseSlice + swz;
-    static_for<0, kDenseRB>([&](auto rbc) {
-      constexpr int RB = decltype(rbc)::value;
-      if (RB < nrb) {
-        const int off = (16 * RB + lr) * 64;
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + off));
-        const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + kDenseSlice + off));
-        acc[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[RB], 0, 0, 0);
-        acc[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[RB], 0, 0, 0);
-        acc[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[RB], 0, 0, 0);
+    // row blocks in groups of 4: the fragments of group q + 1 are read while the products of group q issue
+    // (the scheduling barrier keeps the compiler from hoisting every fragment read of the slice at once)
+    constexpr int GR = 4, NG = (NRB + GR - 1) / GR;
+    bf16x8 fh[2][GR], fl[2][GR];
+    static_for<0, NG + 1>([&](auto qc) {
+      constexpr int Q = decltype(qc)::value;
+      if constexpr (Q < NG) {
+        static_for<0, GR>([&](auto jc) {
+          constexpr int J = decltype(jc)::value, RB = GR * Q + J;
+          if constexpr (RB < NRB) {
+            const int off = (16 * RB + lr) * 64;
+            fh[Q & 1][J] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + off));
+            fl[Q & 1][J] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(src + kDenseSlice + off));
+          }
+        });
+      }
+      if constexpr (Q > 0) {
+        static_for<0, GR>([&](auto jc) {
+          constexpr int J = decltype(jc)::value, RB = GR * (Q - 1) + J;
+          if constexpr (RB < NRB) {
+            const bf16x8 ah = fh[(Q - 1) & 1][J], al = fl[(Q - 1) & 1][J];
+            acc0[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, acc0[RB], 0, 0, 0);
+            acc1[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, acc1[RB], 0, 0, 0);
+            acc0[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, acc0[RB], 0, 0, 0);
+            acc1[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, acc1[RB], 0, 0, 0);
+            acc0[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, acc0[RB], 0, 0, 0);
+            acc1[RB] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, acc1[RB], 0, 0, 0);
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
       }
     });
-    if (ks + 1 < nks) GMM_DENSE_STORE((ks + 1) & 1);  // the other buffer, last read before the previous barrier
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's fills of the next slice have landed
     __syncthreads();
   }
-#undef GMM_DENSE_LOAD
-#undef GMM_DENSE_STORE
   // fold: accumulator register i of lane (lr, lk) in row block rb is row 16 rb + 4 lk + i
+#pragma unroll
+  for (int r = 0; r < kDenseAR; ++r) {
+    const int i = tid + kDenseThreads * r;
+    if (i < N * kDenseCols) {
+      sA[i] = areg[r];
+      sNL0[i] = sNL1[i] = cplx<float>{0.f, 0.f};
+    }
+  }
   const int NN = N * N, col = tid & 127, g = tid >> 7;
-  static_for<0, (kDenseRB + 3) / 4>([&](auto qc) {
-    constexpr int Q = decltype(qc)::value;  // rows 64 Q .. 64 Q + 63
-    if (4 * Q < nrb) {
-      __syncthreads();  // the K loop (first piece) or the previous fold has finished with the LDS
+  cplx<float>* myNL = g ? sNL1 : sNL0;
+  static_for<0, (NRB + 3) / 4>([&](auto qc) {
+    constexpr int Q = decltype(qc)::value;  // rows 64 Q .. 64 Q + 63: pairs pl = 32 Q .. 32 Q + 31
+    if (32 * Q < NN) {
+      __syncthreads();  // the previous piece's fold (or the K loop) has finished with the LDS
+      static_for<0, 4>([&](auto jc) {
+        constexpr int J = decltype(jc)::value;
+        if constexpr (4 * Q + J < NRB) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (4 * Q + j < kDenseRB)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            sC[(16 * j + 4 * lk + i) * kDenseCols + 16 * wave + lr] = acc[min(4 * Q + j, kDenseRB - 1)][i];
-      __syncthreads();
-      // pairs pl = p N + l of this piece, walked with (p, l) carried (wave-uniform, no division in the loop)
-      const int r2end = min(32, NN - 32 * Q);
-      int p = (32 * Q) / N, l = 32 * Q - p * N;
-      for (int r2 = 0; r2 < r2end; ++r2) {
-        if ((p & 3) == g) {
-          const float cr = sC[(2 * r2) * kDenseCols + col], ci = sC[(2 * r2 + 1) * kDenseCols + col];
-          const cplx<float> a = sA[l * kDenseCols + col];
-          cplx<float>& o = sNL[p * kDenseCols + col];
-          o.re += cr * a.re - ci * a.im;
-          o.im += cr * a.im + ci * a.re;
+          for (int i = 0; i < 4; ++i) {
+            sC[(16 * J + 4 * lk + i) * kDenseCS + 32 * wave + lr] = acc0[4 * Q + J][i];
+            sC[(16 * J + 4 * lk + i) * kDenseCS + 32 * wave + 16 + lr] = acc1[4 * Q + J][i];
+          }
         }
-        if (++l == N) l = 0, ++p;
+      });
+      __syncthreads();
+      // thread (t, g) takes pairs pl = 32 Q + 16 g .. + 15 = p N + l in order, summing C_pl A_l in registers
+      // and adding each mode's partial sum to its own NL partial when p changes or the range ends
+      const int pl0 = 32 * Q + 16 * g, cnt = min(16, NN - pl0);
+      if (cnt > 0) {
+        int p = pl0 / N, l = pl0 - p * N;
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (r < cnt) {
+            const int r2 = 16 * g + r;
+            const float cr = sC[(2 * r2) * kDenseCS + col], ci = sC[(2 * r2 + 1) * kDenseCS + col];
+            const cplx<float> a = sA[l * kDenseCols + col];
+            sr += cr * a.re - ci * a.im;
+            si += cr * a.im + ci * a.re;
+            if (++l == N || r + 1 == cnt) {
+              myNL[p * kDenseCols + col].re += sr;
+              myNL[p * kDenseCols + col].im += si;
+              sr = si = 0.f;
+              if (l == N) l = 0, ++p;
+            }
+          }
+        }
       }
     }
   });
   __syncthreads();
-  for (int i = tid; i < N * kDenseCols; i += 512) Aj[(size_t)(i >> 7) * Nt + (i & 127)] = sNL[i];
+  for (int i = tid; i < N * kDenseCols; i += kDenseThreads) {
+    const cplx<float> a = sNL0[i], b = sNL1[i];
+    Aj[(size_t)(i >> 7) * Nt + (i & 127)] = cplx<float>{a.re + b.re, a.im + b.im};
+  }
 }
 
-hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const float* Bd, cplx<float>* A_NL, int N,
-                                      int KD, int KD32, int rows_pad, int Nt, int count, const Ctrl* ctrl,
-                                      hipStream_t s) {
-  const int nrb = (2 * N * N + 15) / 16;
-  if (N > 15 || KD32 % 32 || KD > KD32 || nrb > kDenseRB || rows_pad < 16 * nrb || Nt % kDenseCols) return hipErrorInvalidValue;
-  const size_t lds = kDenseGBytes + (size_t)2 * N * kDenseCols * sizeof(cplx<float>);
-  static const hipError_t attr =
-      hipFuncSetAttribute((const void*)k_contract_dense_bf16, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(kDenseGBytes + (size_t)2 * 15 * kDenseCols * sizeof(cplx<float>)));
+template <int NRB>
+hipError_t launch_dense_bf16_nrb(const void* Ghi, const void* Glo, const float* Bd, cplx<float>* A_NL, int N, int KD,
+                                 int KD32, int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+  const size_t lds = kDenseGBytes;
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void*)k_contract_dense_bf16<NRB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDenseGBytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(k_contract_dense_bf16, dim3(count * (Nt / kDenseCols)), dim3(512), lds, s, (const uint4*)Ghi,
-                     (const uint4*)Glo, Bd, A_NL, N, KD, KD32, nrb, Nt, ctrl);
+  hipLaunchKernelGGL((k_contract_dense_bf16<NRB>), dim3(count * (Nt / kDenseCols)), dim3(kDenseThreads), lds, s,
+                     (const uint4*)Ghi, (const uint4*)Glo, Bd, A_NL, N, KD, KD32, Nt, ctrl);
   return hipGetLastError();
+}
+
+// G hi/lo must hold kDenseRB * 16 rows (zero beyond 2 N^2) of KD32 bf16 each.
+hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const float* Bd, cplx<float>* A_NL, int N,
+                                      int KD, int KD32, int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+  if (N > 15 || KD32 % 32 || KD > KD32 || Nt % kDenseCols) return hipErrorInvalidValue;
+  const int rows = 2 * N * N;
+  if (rows <= 128) return launch_dense_bf16_nrb<8>(Ghi, Glo, Bd, A_NL, N, KD, KD32, Nt, count, ctrl, s);
+  if (rows <= 256) return launch_dense_bf16_nrb<16>(Ghi, Glo, Bd, A_NL, N, KD, KD32, Nt, count, ctrl, s);
+  return launch_dense_bf16_nrb<kDenseRB>(Ghi, Glo, Bd, A_NL, N, KD, KD32, Nt, count, ctrl, s);
 }
 
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,

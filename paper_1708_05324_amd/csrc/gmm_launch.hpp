@@ -73,10 +73,11 @@ hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void*
 // KPAD 64 or 128): BF16 split (Va/Vb = V hi/lo [RQ][KPAD] bf16) or FP32 (Va = V^T [KPAD][RQ]).
 hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, const void* Vb, const cplx<float>* A,
                                float* Y, int N, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
-// General-route product C = G B with the BF16 split for BF16X3 plans (G hi/lo [rows_pad][KD32] bf16).
+// General-route product C = G B with the BF16 split for BF16X3 plans (up to 15 modes; G hi/lo
+// [kDenseGRows][KD32] bf16, rows beyond 2 N^2 zero).
+constexpr int kDenseGRows = 464;
 hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const float* Bd, cplx<float>* A_NL, int N,
-                                      int KD, int KD32, int rows_pad, int Nt, int count, const Ctrl* ctrl,
-                                      hipStream_t s);
+                                      int KD, int KD32, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 

@@ -316,7 +316,7 @@ struct Runner {
         if (P->bf16) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT,
                      gmm::launch_contract_dense_bf16(P->Ghi, P->Glo, (const float*)P->Bp, W, P->N, P->KD, P->KD32,
-                                                     P->rows_pad, P->nt, count, ctrl, P->stream));
+                                                     P->nt, count, ctrl, P->stream));
           done = true;
         }
       }
@@ -801,8 +801,8 @@ int upload_dense(gmm_plan_s* P, FK sk, FR sr) {
   GMM_HIP(hipMemcpy(P->G, g.data(), g.size() * sizeof(T), hipMemcpyHostToDevice));
   P->KD32 = (P->KD + 31) / 32 * 32;
   if (P->bf16) {  // hi/lo split of G for the BF16X3 product, K padded to 32 with zeros
-    std::vector<uint16_t> hi((size_t)P->rows_pad * P->KD32, 0), lo((size_t)P->rows_pad * P->KD32, 0);
-    for (int r = 0; r < P->rows_pad; ++r)
+    std::vector<uint16_t> hi((size_t)gmm::kDenseGRows * P->KD32, 0), lo((size_t)gmm::kDenseGRows * P->KD32, 0);
+    for (int r = 0; r < std::min(P->rows_pad, gmm::kDenseGRows); ++r)
       for (int k = 0; k < P->KD; ++k) {
         const float x = (float)g[(size_t)r * P->KD + k];
         const uint16_t h = host_bf16(x);

@@ -297,6 +297,7 @@ GENERAL_CASES = [  # (groups, nt, fR, complex S, distinct S^R)
     (2, 256, 0.0, True, False),      # 3 modes, Kerr only, complex non-symmetric S
     (2, 512, 0.18, False, True),     # 3 modes, real S without the (m, n) symmetry, S^R != S^K
     (3, 1024, 0.18, True, True),     # 6 modes, complex S^K != S^R, Raman + shock
+    (4, 512, 0.18, True, True),      # 10 modes: 200 output rows (the BF16 kernel's middle row-block count)
     (5, 256, 0.18, True, True),      # 15 modes: 450 output rows, K = 480
 ]
 
