@@ -37,6 +37,12 @@ Conventions (readings of the paper; each is pinned by a test):
     C_p = i sum_n Q_np A_n with a z-independent coupling matrix Q, also beside
     the nonlinear term (so the MPA treats it inside its integrand, which needs
     L = M dz << 1/|Q|, the same regime as for the nonlinear length).
+  * or, with ``Q_linear``, the same term moved into the linear operator: per
+    frequency L(w) = diag(D_w) + i Q^T, an N x N matrix, and the change of
+    variables of Sec. III.D uses its matrix exponential exp(L(w) z) in place of
+    exp(D_w z).  C is linear and z-independent, so Eq. (cov) and Eq. (MPA_eq)
+    carry over unchanged with that operator; the coupling is then exact for
+    any step size and only the nonlinear term is left in the integrand.
 """
 from __future__ import annotations
 
@@ -71,6 +77,7 @@ class Model:
     gain: np.ndarray | None = None   # [N] small-signal field gain g_p (1/m), or None
     I_sat: float = math.inf           # saturation fluence (J/m^2) of the gain term
     Q: np.ndarray | None = None      # [N, N] linear coupling Q_np (1/m), C_p = i sum_n Q_np A_n, or None
+    Q_linear: bool = False           # True: C in the linear operator (matrix exponential), else in the integrand
 
     @property
     def n_modes(self) -> int:
@@ -173,7 +180,7 @@ def nonlinear_operator(At: np.ndarray, model: Model, omega: np.ndarray, H) -> np
     out = 1j * model.gamma_hat * shock * to_spectrum(NL)
     if model.gain is not None:
         out = out + to_spectrum(gain_term(A, model))
-    if model.Q is not None:
+    if model.Q is not None and not model.Q_linear:
         out = out + 1j * (np.asarray(model.Q).T @ At)          # C_p = i sum_n Q_np A~_n (linear in A)
     return out
 
@@ -191,6 +198,25 @@ class _Ops:
 
     def N(self, At):
         return nonlinear_operator(At, self.model, self.omega, self.H)
+
+    def lin(self, z: float, At: np.ndarray) -> np.ndarray:
+        """exp(L z) A~: the linear propagator over z (z may be negative).
+
+        Diagonal case: exp(D_w z) A~.  With ``Q_linear``: per frequency the
+        matrix exponential of L(w) z, L(w) = diag(D_w) + i Q^T, applied to the
+        mode vector A~(w)."""
+        if self.model.Q is None or not self.model.Q_linear:
+            return np.exp(self.D * z) * At
+        from scipy.linalg import expm
+        key = float(z)
+        cache = self.__dict__.setdefault("_expm", {})
+        if key not in cache:
+            Lw = np.zeros((self.omega.size,) + (self.D.shape[0],) * 2, dtype=np.complex128)
+            Lw[:] = 1j * np.asarray(self.model.Q, dtype=np.complex128).T
+            idx = np.arange(self.D.shape[0])
+            Lw[:, idx, idx] += self.D.T
+            cache[key] = expm(Lw * z)                   # [Nt, N, N]
+        return np.einsum("kpq,qk->pk", cache[key], At)
 
 
 def small_steps(L: float, dz: float) -> tuple[int, float]:
@@ -216,12 +242,12 @@ def mpa_large_step(At0: np.ndarray, ops: _Ops, dz: float, M: int, tol: float = 1
     """One large step L = M dz of the MPA from z0 (Sec. III.D).
 
     psi_p(z, w) = A~_p(z, w) exp[-D_w (z - z0)]   (Eq. (cov)) and, from Eq. (MPA_eq),
-    psi(z_j) = psi(z0) + int_{z0}^{z_j} exp[-D_w (z'-z0)] N~[A(z')] dz'.
+    psi(z_j) = psi(z0) + int_{z0}^{z_j} exp[-D_w (z'-z0)] N~[A(z')] dz'
+    (with ``Q_linear``: exp(-L(w)(z - z0)) applied to the mode vector instead).
     Iterate: start from psi^(1)(z_j) = psi(z0); evaluate the integrands at all
     z_j (the parallel part); accumulate them with the trapezoid rule; repeat
     until the relative change of psi is below ``tol``.  Return A~(z0 + M dz).
     """
-    E = [np.exp(ops.D * (j * dz)) for j in range(M + 1)]
     psi0 = At0
     I0 = ops.N(At0)                                   # integrand at z0 (exp(-D*0) = 1)
     psi = [psi0.copy() for _ in range(M)]             # psi^(1)(z_j), j = 1..M
@@ -230,7 +256,7 @@ def mpa_large_step(At0: np.ndarray, ops: _Ops, dz: float, M: int, tol: float = 1
     converged = False
     while True:
         n += 1
-        I = [ops.N(E[j] * psi[j - 1]) / E[j] for j in range(1, M + 1)]
+        I = [ops.lin(-j * dz, ops.N(ops.lin(j * dz, psi[j - 1]))) for j in range(1, M + 1)]
         new = []
         run = np.zeros_like(psi0)                     # sum_{k=1}^{j-1} I_k
         for j in range(1, M + 1):
@@ -252,7 +278,7 @@ def mpa_large_step(At0: np.ndarray, ops: _Ops, dz: float, M: int, tol: float = 1
             break
         elif n >= max_iter:
             break
-    return E[M] * psi[M - 1], n, eps_hist, converged
+    return ops.lin(M * dz, psi[M - 1]), n, eps_hist, converged
 
 
 def mpa_propagate(A0: np.ndarray, model: Model, L: float, dz: float, M: int,
@@ -291,18 +317,17 @@ def trapezoid_propagate(A0: np.ndarray, model: Model, L: float, dz: float,
     """
     ops = _Ops(model, A0.shape[1])
     n_small, dz = small_steps(L, dz)
-    E = np.exp(ops.D * dz)
     At = to_spectrum(A0.astype(np.complex128))
     for _ in range(n_small):
         f0 = ops.N(At)
         psi1 = At.copy()
         for _it in range(max_picard):
-            nxt = At + 0.5 * dz * (f0 + ops.N(E * psi1) / E)
+            nxt = At + 0.5 * dz * (f0 + ops.lin(-dz, ops.N(ops.lin(dz, psi1))))
             ch = np.linalg.norm(nxt - psi1) / max(np.linalg.norm(nxt), 1e-300)
             psi1 = nxt
             if ch < tol:
                 break
-        At = E * psi1
+        At = ops.lin(dz, psi1)
     return to_time(At)
 
 
@@ -311,15 +336,15 @@ def rk4ip_propagate(A0: np.ndarray, model: Model, L: float, dz: float):
     """4th-order Runge-Kutta in the interaction picture (Hult, JLT 25, 2007)."""
     ops = _Ops(model, A0.shape[1])
     n_small, h = small_steps(L, dz)
-    Eh = np.exp(ops.D * (h / 2.0))
+    Eh = lambda x: ops.lin(h / 2.0, x)                # noqa: E731  exp(L h/2)
     At = to_spectrum(A0.astype(np.complex128))
     for _ in range(n_small):
-        AI = Eh * At
-        k1 = Eh * ops.N(At)
+        AI = Eh(At)
+        k1 = Eh(ops.N(At))
         k2 = ops.N(AI + 0.5 * h * k1)
         k3 = ops.N(AI + 0.5 * h * k2)
-        k4 = ops.N(Eh * (AI + h * k3))
-        At = Eh * (AI + h * (k1 / 6.0 + k2 / 3.0 + k3 / 3.0)) + h * k4 / 6.0
+        k4 = ops.N(Eh(AI + h * k3))
+        At = Eh(AI + h * (k1 / 6.0 + k2 / 3.0 + k3 / 3.0)) + h * k4 / 6.0
     return to_time(At)
 
 

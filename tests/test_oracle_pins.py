@@ -482,3 +482,103 @@ def test_hermitian_coupling_conserves_energy_in_the_converged_mpa():
     drift = [abs(O.energy(O.mpa_propagate(A0, m, 0.02, h, 5, tol=1e-15, max_iter=80), dt) / O.energy(A0, dt) - 1)
              for h in (0.002, 0.001)]
     assert 3.0 < drift[0] / drift[1] < 5.0
+
+
+# ------------------------------------------------------ linear coupling inside the linear operator (Sec. III.F)
+def _coupler_A0(nt, dt):
+    return np.stack([gauss(nt, dt, 500e-15), 0 * gauss(nt, dt, 500e-15)])
+
+
+def test_coupling_in_the_linear_operator_is_exact_for_any_step():
+    """With C_p = i sum_n Q_np A_n moved into the linear operator, the MPA's
+    change of variables propagates it exactly: at n2 = 0 the two-mode coupler
+    reaches the coupled-mode closed form (k / W)^2 sin^2(W z) with three small
+    steps over more than one beat length, where the integrand treatment of the
+    same term is off by its O(dz^2) error."""
+    nt, dt = 128, 50e-15
+    k, d = 30.0, 40.0
+    W = math.sqrt(k ** 2 + (d / 2) ** 2)
+    L = 0.05
+    want = (k / W) ** 2 * math.sin(W * L) ** 2
+    A0 = _coupler_A0(nt, dt)
+    m = mk([[0.0, 0.0, 0.0], [d, 0.0, 0.0]], dt=dt, n2=0.0)
+    m.Q, m.Q_linear = np.array([[0.0, k], [k, 0.0]]), True
+    A = O.mpa_propagate(A0, m, L, L / 3, 3, tol=1e-15, max_iter=50)
+    assert abs(O.energy(A[1:], dt) / O.energy(A0, dt) - want) < 1e-12
+    m.Q_linear = False
+    A = O.mpa_propagate(A0, m, L, L / 3, 3, tol=1e-15, max_iter=50)
+    assert abs(O.energy(A[1:], dt) / O.energy(A0, dt) - want) > 1e-3
+
+
+def test_linear_operator_with_coupling_against_brute_force_rk4():
+    """Three modes, complex Hermitian Q (so Q^T != Q and a transposed operand
+    shows), delays, GVD and phase mismatch: the Q_linear propagator of the
+    oracle equals a plain RK4 integration, 4000 steps, of
+    dA~_p/dz = D_p(w) A~_p + i sum_n Q_np A~_n written out mode by mode."""
+    rng = np.random.default_rng(11)
+    N, nt, dt = 3, 64, 40e-15
+    betas = np.array([[0.0, 0.0, 0.02e-24], [60.0, 2e-13, 0.01e-24], [-40.0, -1e-13, 0.03e-24]])
+    Qh = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * 15.0
+    Q = Qh + Qh.conj().T
+    m = mk(betas, dt=dt, n2=0.0)
+    m.Q, m.Q_linear = Q, True
+    A0 = np.stack([gauss(nt, dt, 300e-15), 0.5j * gauss(nt, dt, 200e-15, 1e-13), 0.3 * gauss(nt, dt, 250e-15)])
+    L = 0.04
+    got = O.to_spectrum(O.mpa_propagate(A0, m, L, L / 4, 4, tol=1e-15, max_iter=60))
+    om = O.omega_grid(nt, dt)
+    Dp = np.zeros((N, nt), complex)
+    for p in range(N):
+        Dp[p] = 1j * (betas[p, 0] + betas[p, 1] * om + betas[p, 2] * om ** 2 / 2.0)
+
+    def rhs(X):
+        out = Dp * X
+        for p in range(N):
+            for n in range(N):
+                out[p] = out[p] + 1j * Q[n, p] * X[n]
+        return out
+    X = O.to_spectrum(A0)
+    steps = 4000
+    h = L / steps
+    for _ in range(steps):
+        k1 = rhs(X)
+        k2 = rhs(X + 0.5 * h * k1)
+        k3 = rhs(X + 0.5 * h * k2)
+        k4 = rhs(X + h * k3)
+        X = X + h * (k1 + 2 * k2 + 2 * k3 + k4) / 6.0
+    assert relmax(got, X) < 1e-9
+
+
+def test_linear_and_integrand_coupling_solve_the_same_equation():
+    """With Kerr nonlinearity on, the two placements of C are integrators of
+    one equation: RK4IP (4th order) gives the same field either way at a fine
+    step, and the Q_linear MPA converges to it at second order."""
+    rng = np.random.default_rng(5)
+    N, nt, dt = 3, 128, 30e-15
+    fib = synth.GrinFiber()
+    S = synth.coupling_tensor(fib, synth.hg_modes(2))
+    betas = np.array([[0.0, 0.0, 0.02e-24], [50.0, 1e-13, 0.02e-24], [50.0, 1e-13, 0.02e-24]])
+    Qh = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) * 10.0
+    A0 = np.stack([gauss(nt, dt, 200e-15) * 300.0, gauss(nt, dt, 250e-15) * 150.0, 100j * gauss(nt, dt, 200e-15)])
+    m = mk(betas, S=S, dt=dt)
+    m.Q = Qh + Qh.conj().T
+    L = 0.01
+    m.Q_linear = True
+    ref = O.rk4ip_propagate(A0, m, L, L / 200)
+    m.Q_linear = False
+    assert relmax(O.rk4ip_propagate(A0, m, L, L / 200), ref) < 1e-9
+    m.Q_linear = True
+    errs = [relmax(O.mpa_propagate(A0, m, L, L / n, 5, tol=1e-14, max_iter=60), ref) for n in (10, 20)]
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_linear_coupling_with_zero_q_is_the_uncoupled_operator():
+    """Q = 0 in the linear operator reduces exp(L z) to exp(D_w z)."""
+    nt, dt = 128, 30e-15
+    fib = synth.GrinFiber()
+    S = synth.coupling_tensor(fib, synth.hg_modes(2))
+    betas = np.array([[0.0, 0.0, 0.02e-24], [50.0, 1e-13, 0.02e-24], [50.0, 1e-13, 0.02e-24]])
+    A0 = np.stack([gauss(nt, dt, 200e-15) * 300.0, gauss(nt, dt, 250e-15) * 150.0, 100j * gauss(nt, dt, 200e-15)])
+    m = mk(betas, S=S, dt=dt)
+    ref = O.mpa_propagate(A0, m, 0.01, 0.001, 5, fixed_iters=3)
+    m.Q, m.Q_linear = np.zeros((3, 3)), True
+    assert relmax(O.mpa_propagate(A0, m, 0.01, 0.001, 5, fixed_iters=3), ref) < 1e-12
