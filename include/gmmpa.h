@@ -165,8 +165,30 @@ int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat);
  *               real, or complex when q_complex = 1 ([N][N][2] doubles).
  *               Copied.  NULL turns the term off.
  * Returns GMM_ERR_ARG for bad values, GMM_ERR_UNSUPPORTED above 22 modes.
+ * Turns off the form of gmm_plan_set_coupling_exact (one placement at a time).
  */
 int gmm_plan_set_coupling(gmm_plan plan, const double* Q, int q_complex);
+
+/*
+ * gmm_plan_set_coupling_exact - the same coupling term (Sec. III.F) placed in
+ * the linear operator instead of the integrand: per frequency
+ *   L(w) = diag(D_w) + i Q^T  = i H(w),  H = diag(d(w)) + Q^T Hermitian,
+ * and the change of variables of Sec. III.D (Eq. (cov), Eq. (MPA_eq)) uses
+ * exp(L(w) z) = U(w) exp(i lam(w) z) U(w)^H.  The coupling is then exact for any
+ * step; only the nonlinear term stays in the integrand.  The plan computes the
+ * eigen-decomposition of H at every frequency bin (FP64, host threads) and
+ * keeps U (field precision, N^2 Nt complex) and lam (FP64) on the device;
+ * gmm_propagate iterates in the eigenbasis (two per-frequency mode mixings per
+ * evaluation, one at each end of the propagation).
+ *   Q         : as for gmm_plan_set_coupling; must be Hermitian,
+ *               Q_np = conj(Q_pn) to 1e-12 of its largest entry (real: symmetric).
+ *               Copied.  NULL turns the term off.
+ * Returns GMM_ERR_ARG for bad values or a non-Hermitian Q, GMM_ERR_UNSUPPORTED
+ * above 22 modes or with the gain term on.  gmm_propagate_rk4ip returns
+ * GMM_ERR_UNSUPPORTED while it is on; gmm_nonlinear is unaffected (it has no
+ * linear part).  Turns off the form of gmm_plan_set_coupling.
+ */
+int gmm_plan_set_coupling_exact(gmm_plan plan, const double* Q, int q_complex);
 
 /*
  * gmm_nonlinear - the integrand factor of Eq. (MPA_eq) for `count` fields:

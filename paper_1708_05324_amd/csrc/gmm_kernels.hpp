@@ -85,13 +85,85 @@ __global__ __launch_bounds__(256) void k_phase_table(cplx<T>* __restrict__ E, co
   E[e] = expi_reduced<T>(disp_phase(coef + p * nb, nb, omega_of(k, nt, domega)) * ((double)j * dz));
 }
 
+// Linear coupling inside the linear operator (Sec. III.F term C = i sum_n Q_np A_n
+// with Sec. III.D's change of variables): per frequency L(w) = diag(D_w) + i Q^T
+// = i H(w), H Hermitian, H = U diag(lambda) U^H.  The iterate is kept in the
+// eigenbasis, where exp(L z) is the diagonal exp(i lambda z): this table.
+// E[j][q][k] = exp(i lambda_q(w_k) j dz), lam [N][nt] in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phase_table_lam(cplx<T>* __restrict__ E, const double* __restrict__ lam,
+                                                         int N, int nt, long total, double dz) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long row = e / nt;
+  const int k = (int)(e - row * nt), q = (int)(row % N), j = (int)(row / N);
+  E[e] = expi_reduced<T>(lam[(size_t)q * nt + k] * ((double)j * dz));
+}
+
+// Per-frequency mode mixing with the eigenvectors U(w) ([N][N][nt], column q =
+// eigenvector q), for sub-steps c < count:
+//   BACK = false: dst_c(w) = U(w) (E_{j0+c}(w) .* src_c(w))     (eigenbasis -> modes)
+//   BACK = true:  dst_c(w) = conj(E_{j0+c}(w)) .* (U(w)^H src_c(w))  (modes -> eigenbasis)
+// E = nullptr: no phase.  src row c at src + c * src_jrows * nt (src_jrows N or
+// 0); dst rows [count][N][nt]; dst may be src.  One block of 256 threads owns W
+// frequencies for every sub-step: the N x N x W tile of U (or U^H) is staged in
+// LDS once, then per sub-step the N x W source tile, and thread (w, g) forms the
+// rows p = g mod (256 / W) of its frequency.
+template <typename T, int W, bool BACK>
+__global__ __launch_bounds__(256) void k_mode_mix(const cplx<T>* src, long src_jrows, cplx<T>* dst,
+                                                  const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ E,
+                                                  int j0, int N, int nt, int count, const Ctrl* ctrl) {
+  constexpr int G = 256 / W;
+  if (skip_iteration(ctrl)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* sU = reinterpret_cast<cplx<T>*>(smem_raw);  // [N][N][W]: M_pq(k0 + w)
+  cplx<T>* sS = sU + N * N * W;                         // [N][W]
+  const int tid = threadIdx.x, w = tid % W, g = tid / W;
+  const int k0 = blockIdx.x * W;
+  for (int i = tid; i < N * N * W; i += 256) {
+    const int pq = i / W, ww = i - pq * W, p = pq / N, q = pq - p * N;
+    if (BACK) {  // (U^H)_pq = conj(U_qp)
+      const cplx<T> u = U[((size_t)q * N + p) * nt + k0 + ww];
+      sU[i] = cplx<T>{u.re, -u.im};
+    } else {
+      sU[i] = U[((size_t)p * N + q) * nt + k0 + ww];
+    }
+  }
+  for (int c = 0; c < count; ++c) {
+    __syncthreads();  // the previous sub-step's products are done with sS
+    for (int i = tid; i < N * W; i += 256) {
+      const int q = i / W, ww = i - q * W;
+      const size_t k = (size_t)k0 + ww;
+      cplx<T> v = src[((size_t)c * src_jrows + q) * nt + k];
+      if (!BACK && E != nullptr) v = cmul(v, E[((size_t)(j0 + c) * N + q) * nt + k]);
+      sS[i] = v;
+    }
+    __syncthreads();
+    for (int p = g; p < N; p += G) {
+      cplx<T> acc{T(0), T(0)};
+      for (int q = 0; q < N; ++q) {
+        const cplx<T> m = sU[(p * N + q) * W + w], x = sS[q * W + w];
+        acc.re += m.re * x.re - m.im * x.im;
+        acc.im += m.re * x.im + m.im * x.re;
+      }
+      const size_t o = ((size_t)c * N + p) * nt + k0 + w;
+      if (BACK && E != nullptr) {
+        const cplx<T> e = E[((size_t)(j0 + c) * N + p) * nt + k0 + w];
+        acc = cmul(acc, cplx<T>{e.re, -e.im});
+      }
+      dst[o] = acc;
+    }
+  }
+}
+
 // a1: A_j(t) = FFT_{-}[ exp(D_w z_j) psi_j ],  z_j = (j0 + jj) dz, the factor
-// read from the phase table (E = nullptr: no phase, z = 0).
+// read from the phase table (E = nullptr: no phase, z = 0).  A may be psi
+// (each block reads its whole row before the transform writes it).
 // grid (N, count); psi row (jj, p) at psi + (jj * psi_jrows + p) * Nt, where
 // psi_jrows is a row count: N for one field per sub-step, 0 to reuse psi_0.
 template <typename T, int LOGN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
-    const cplx<T>* __restrict__ psi, long psi_jrows, cplx<T>* __restrict__ A, const cplx<T>* __restrict__ E, int j0,
+    const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* __restrict__ E, int j0,
     const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;

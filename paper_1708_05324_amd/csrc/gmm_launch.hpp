@@ -17,6 +17,12 @@ struct Launch {
   // E[j][p][k] = exp(i (beta_p(w_k) - beta_0) j dz), j < rows
   static hipError_t phase_table(cplx<T>* E, const double* coef, int nb, int N, int nt, int rows, double dz,
                                 double domega, hipStream_t s);
+  // Eigenbasis table of the coupled linear operator: E[j][q][k] = exp(i lam_q(w_k) j dz), j < rows
+  static hipError_t phase_table_lam(cplx<T>* E, const double* lam, int N, int nt, int rows, double dz,
+                                    hipStream_t s);
+  // back = false: dst = U (E .* src); back = true: dst = conj(E) .* (U^H src), per frequency (E may be null)
+  static hipError_t mode_mix(bool back, const cplx<T>* src, long src_jrows, cplx<T>* dst, const cplx<T>* U,
+                             const cplx<T>* E, int j0, int N, int nt, int count, const Ctrl* ctrl, hipStream_t s);
   static hipError_t phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E, int N,
                                   int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,

@@ -58,6 +58,38 @@ hipError_t Launch<T>::phase_table(cplx<T>* E, const double* coef, int nb, int N,
 }
 
 template <typename T>
+hipError_t Launch<T>::phase_table_lam(cplx<T>* E, const double* lam, int N, int nt, int rows, double dz,
+                                      hipStream_t s) {
+  const long total = (long)rows * N * nt;
+  hipLaunchKernelGGL((k_phase_table_lam<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, E, lam, N, nt,
+                     total, dz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::mode_mix(bool back, const cplx<T>* src, long src_jrows, cplx<T>* dst, const cplx<T>* U,
+                               const cplx<T>* E, int j0, int N, int nt, int count, const Ctrl* ctrl, hipStream_t s) {
+  constexpr int W = sizeof(T) == 4 ? 32 : 16;  // frequencies per block
+  if (N < 1 || N > kGainNmax || nt % W || count < 1) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(N * N + N) * W * sizeof(cplx<T>);
+  const int lds_max = (int)((size_t)(kGainNmax * kGainNmax + kGainNmax) * W * sizeof(cplx<T>));
+  if (back) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, W, true>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_mode_mix<T, W, true>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N, nt,
+                       count, ctrl);
+  } else {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, W, false>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_mode_mix<T, W, false>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N,
+                       nt, count, ctrl);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E,
                                     int N, int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {

@@ -11,6 +11,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <new>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -168,8 +170,14 @@ struct gmm_plan_s {
   // saturating gain (Sec. III.F): G = Mg A per sub-step
   std::vector<std::complex<double>> SRh;  // host copy of S^R (S^K when SR is NULL), [N^4]
   bool gain_on = false;
-  bool coupling_on = false;          // linear mode coupling C_p = i sum_n Q_np A_n
+  bool coupling_on = false;          // linear mode coupling C_p = i sum_n Q_np A_n (in the integrand)
   cplx<double>* Kc = nullptr;        // [N][N] K_pl = i Q_lp
+  // linear coupling inside the linear operator: L(w) = i H(w), H = diag(d(w)) + Q^T = U diag(lam) U^H;
+  // the iterate psi is then kept in the eigenbasis (psi_eig = U^H psi) and E holds exp(i lam j dz)
+  bool cpl_exact = false;
+  void* Uc = nullptr;                // [N][N][nt] eigenvectors (column q = eigenvector q), field precision
+  double* lam = nullptr;             // [N][nt] eigenvalues (1/m)
+  std::vector<double> coefh;         // host copy of coef
   double inv_Isat = 0.0;
   double* gvec = nullptr;               // [N] g_p (1/m)
   cplx<double>* SRd = nullptr;          // [N^4] S^R on the device
@@ -295,8 +303,17 @@ struct Runner {
     if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
     cplx<T>* W = (cplx<T>*)P->work;
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
-    GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
-                                                         P->stream));
+    // coupled linear operator: psi is in the eigenbasis; the modes are U (exp(i lam z) psi)
+    const bool mix = P->cpl_exact && E != nullptr;
+    if (mix) {
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::mode_mix(false, psi, jrows, W, (const cplx<T>*)P->Uc, E, j0, P->N,
+                                                      P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, W, P->N, W, nullptr, P->N, count, j0, tw(),
+                                                           ctrl, P->stream));
+    } else {
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
+                                                           P->stream));
+    }
     const bool linear_terms = P->gain_on || P->coupling_on;
     if (linear_terms) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
       if (count > P->gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
@@ -371,9 +388,12 @@ struct Runner {
       GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
                                                            P->N, P->Np, P->nt, count, ctrl, P->stream));
     }
-    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, E, P->N, count, j0, P->domega,
-                                                           P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
+    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, mix ? nullptr : E, P->N, count, j0,
+                                                           P->domega, P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
                                                            P->prm.self_steepening, tw(), ctrl, P->stream));
+    if (mix)  // back to the eigenbasis, then exp(-i lam z)
+      GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::mode_mix(true, out, P->N, out, (const cplx<T>*)P->Uc, E, j0, P->N,
+                                                         P->nt, count, ctrl, P->stream));
     if (linear_terms)
       GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::gain_add(psi, jrows, E, j0, P->Mg, out, P->N, P->nt, count, ctrl,
                                                        P->stream));
@@ -413,8 +433,11 @@ struct Runner {
       if (rc) return rc;
       P->E_rows = rows;
     }
-    GMM_HIP(Launch<T>::phase_table((cplx<T>*)P->E, P->coef, P->nb, P->N, P->nt, P->E_rows, dz, P->domega,
-                                   P->stream));
+    if (P->cpl_exact)
+      GMM_HIP(Launch<T>::phase_table_lam((cplx<T>*)P->E, P->lam, P->N, P->nt, P->E_rows, dz, P->stream));
+    else
+      GMM_HIP(Launch<T>::phase_table((cplx<T>*)P->E, P->coef, P->nb, P->N, P->nt, P->E_rows, dz, P->domega,
+                                     P->stream));
     P->E_dz = dz;
     return GMM_OK;
   }
@@ -454,6 +477,9 @@ struct Runner {
     GMM_HIP(Launch<T>::fft_rows(P->logn, +1, (const cplx<T>*)A0, (cplx<T>*)P->psi0, (T)(1.0 / P->nt), P->N, tw(),
                                 P->stream));
     if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_in, &s.photons_in))) return rc;
+    if (P->cpl_exact)  // into the eigenbasis of the coupled linear operator (U unitary per frequency)
+      GMM_HIP(Launch<T>::mode_mix(true, (const cplx<T>*)P->psi0, P->N, (cplx<T>*)P->psi0, (const cplx<T>*)P->Uc,
+                                  nullptr, 0, P->N, P->nt, 1, nullptr, P->stream));
     long done = 0;
     int status = GMM_OK;
     while (done < n_small) {
@@ -506,7 +532,8 @@ struct Runner {
       s.evaluations += 1 + (long long)c.iters * m;
       if (c.iters > s.max_iters_seen) s.max_iters_seen = c.iters;
       s.last_eps = c.eps;
-      // A~(z0 + m dz) = exp(D m dz) psi_m
+      // A~(z0 + m dz) = exp(D m dz) psi_m (coupled operator: exp(i lam m dz) psi_m in the eigenbasis, which is
+      // also the next large step's psi(z0) there)
       GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
                                                    (const cplx<T>*)P->E + (size_t)m * nn, nn, P->stream));
       s.large_steps++;
@@ -514,6 +541,9 @@ struct Runner {
       done += m;
       P->prof.cur_step++;
     }
+    if (P->cpl_exact)  // back to the modes
+      GMM_HIP(Launch<T>::mode_mix(false, (const cplx<T>*)P->psi0, P->N, (cplx<T>*)P->psi0, (const cplx<T>*)P->Uc,
+                                  nullptr, 0, P->N, P->nt, 1, nullptr, P->stream));
     if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_out, &s.photons_out))) return rc;
     GMM_HIP(Launch<T>::fft_rows(P->logn, -1, (const cplx<T>*)P->psi0, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
     GMM_HIP(hipStreamSynchronize(P->stream));
@@ -524,6 +554,8 @@ struct Runner {
 
   // Serial RK4IP baseline: n steps of h, four dependent evaluations each.
   int propagate_rk4ip(const void* A0, double L, double dz_req, void* Aout, gmm_stats* st) {
+    if (P->cpl_exact)
+      return fail(GMM_ERR_UNSUPPORTED, "RK4IP with the coupling in the linear operator is not implemented");
     const long nn = (long)P->N * P->nt;
     const double r = L / dz_req;
     long n_small = (std::fabs(r - std::round(r)) < 1e-9 * std::max(1.0, r)) ? (long)std::llround(r)
@@ -631,6 +663,107 @@ void jacobi_eigen(int n, std::vector<double>& a, std::vector<double>& v) {
 }
 
 // Host bf16 (round to nearest even) of a float.
+// Cyclic Jacobi for a Hermitian n x n matrix a (row-major, overwritten).  Each
+// rotation is the real Jacobi rotation of the phase-adjusted 2 x 2 block,
+// J = [[c, s e^{i phi}], [-s e^{-i phi}, c]] on columns (p, q), a_pq = |a_pq| e^{i phi}:
+// a <- J^H a J, v <- v J.  On return the diagonal of a holds the eigenvalues
+// and the columns of v (multiplied from the right) the eigenvectors.
+void hermitian_jacobi(int n, std::complex<double>* a, std::complex<double>* v) {
+  using C = std::complex<double>;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) (p == q ? diag : off) += std::norm(a[p * n + q]);
+    if (off <= 1e-32 * diag || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const C apq = a[p * n + q];
+        const double b = std::abs(apq);
+        if (b == 0.0) continue;
+        const C ph = apq / b;
+        const double app = a[p * n + p].real(), aqq = a[q * n + q].real();
+        const double tau = (aqq - app) / (2.0 * b);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        const C sp = sn * ph, sm = sn * std::conj(ph);
+        for (int k = 0; k < n; ++k) {
+          const C akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - sm * akq;
+          a[k * n + q] = sp * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const C apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - sp * aqk;
+          a[q * n + k] = sm * apk + c * aqk;
+        }
+        a[p * n + q] = a[q * n + p] = 0.0;
+        a[p * n + p] = app - t * b;
+        a[q * n + q] = aqq + t * b;
+        for (int k = 0; k < n; ++k) {
+          const C vkp = v[k * n + p], vkq = v[k * n + q];
+          v[k * n + p] = c * vkp - sm * vkq;
+          v[k * n + q] = sp * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+// Eigen-decomposition of H(w_k) = diag(d(w_k)) + Q^T for every frequency bin
+// (d_p = dispersion phase of mode p, Qc[n * N + p] = Q_np): lam [N][nt],
+// U [N][N][nt] (U[(p N + q) nt + k] = component p of eigenvector q).  Bins are
+// split over host threads; inside a chunk each bin starts from the previous
+// bin's eigenvectors (B = V^H H V is then nearly diagonal).
+void coupled_eigen(const gmm_plan_s* P, const std::vector<std::complex<double>>& Qc, std::vector<double>& lam,
+                   std::vector<std::complex<double>>& U) {
+  using C = std::complex<double>;
+  const int N = P->N, nt = P->nt, nb = P->nb;
+  lam.assign((size_t)N * nt, 0.0);
+  U.assign((size_t)N * N * nt, C(0.0));
+  auto work = [&](int k_begin, int k_end) {
+    std::vector<C> H((size_t)N * N), B((size_t)N * N), T((size_t)N * N), V((size_t)N * N, C(0.0));
+    for (int p = 0; p < N; ++p) V[(size_t)p * N + p] = 1.0;
+    for (int k = k_begin; k < k_end; ++k) {
+      const double w = (double)(k < nt / 2 ? k : k - nt) * P->domega;
+      for (int p = 0; p < N; ++p)
+        for (int n = 0; n < N; ++n) H[(size_t)p * N + n] = Qc[(size_t)n * N + p];
+      for (int p = 0; p < N; ++p) {
+        double acc = 0.0;
+        for (int n = nb - 1; n >= 0; --n) acc = acc * w + P->coefh[(size_t)p * nb + n];
+        H[(size_t)p * N + p] += acc;
+      }
+      // B = V^H H V
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          C acc = 0.0;
+          for (int l = 0; l < N; ++l) acc += H[(size_t)i * N + l] * V[(size_t)l * N + j];
+          T[(size_t)i * N + j] = acc;
+        }
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          C acc = 0.0;
+          for (int l = 0; l < N; ++l) acc += std::conj(V[(size_t)l * N + i]) * T[(size_t)l * N + j];
+          B[(size_t)i * N + j] = acc;
+        }
+      for (int i = 0; i < N; ++i)  // exactly Hermitian before the rotations
+        for (int j = i + 1; j < N; ++j) {
+          const C m = 0.5 * (B[(size_t)i * N + j] + std::conj(B[(size_t)j * N + i]));
+          B[(size_t)i * N + j] = m;
+          B[(size_t)j * N + i] = std::conj(m);
+        }
+      hermitian_jacobi(N, B.data(), V.data());
+      for (int q = 0; q < N; ++q) {
+        lam[(size_t)q * nt + k] = B[(size_t)q * N + q].real();
+        for (int p = 0; p < N; ++p) U[((size_t)p * N + q) * nt + k] = V[(size_t)p * N + q];
+      }
+    }
+  };
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nth = std::max(1, std::min({hw, 16, nt / 64}));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) pool.emplace_back(work, (int)((long)nt * t / nth), (int)((long)nt * (t + 1) / nth));
+  for (auto& th : pool) th.join();
+}
+
 uint16_t host_bf16(float x) {
   uint32_t u;
   std::memcpy(&u, &x, 4);
@@ -847,6 +980,7 @@ void destroy(gmm_plan_s* P) {
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
                   P->G, P->Ghi, P->Glo, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
+                  P->Uc, (void*)P->lam,
                   (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
@@ -966,6 +1100,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
       coef[(size_t)q * P->nb + n] = b / fact;
     }
   }
+  P->coefh = coef;
   if ((rc = dev_alloc(&P->const_bytes, &P->coef, coef.size() * sizeof(double)))) return bail(rc);
   if (hipMemcpy(P->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(GMM_ERR_HIP, "copy of dispersion coefficients failed"));
@@ -1070,6 +1205,8 @@ int gmm_plan_set_gain(gmm_plan plan, const double* g, double I_sat) {
     return GMM_OK;
   }
   if (!(I_sat > 0)) return fail(GMM_ERR_ARG, "I_sat must be > 0 (infinity: no saturation)");
+  if (plan->cpl_exact)
+    return fail(GMM_ERR_UNSUPPORTED, "the gain term with the coupling in the linear operator is not implemented");
   if (plan->N > gmm::kGainNmax) return fail(GMM_ERR_UNSUPPORTED, "the gain term supports up to 22 modes");
   for (int p = 0; p < plan->N; ++p)
     if (!std::isfinite(g[p])) return fail(GMM_ERR_ARG, "non-finite gain coefficient");
@@ -1108,7 +1245,68 @@ int gmm_plan_set_coupling(gmm_plan plan, const double* Q, int q_complex) {
   if (!plan->Kc && dev_alloc(&plan->const_bytes, &plan->Kc, K.size() * sizeof(cplx<double>))) return GMM_ERR_NOMEM;
   if (hipMemcpy(plan->Kc, K.data(), K.size() * sizeof(cplx<double>), hipMemcpyHostToDevice) != hipSuccess)
     return fail(GMM_ERR_HIP, "copy of the coupling matrix failed");
+  if (plan->cpl_exact) {  // one placement of the coupling at a time
+    plan->cpl_exact = false;
+    plan->E_dz = std::nan("");
+  }
   plan->coupling_on = true;
+  g_last_error.clear();
+  return GMM_OK;
+}
+
+int gmm_plan_set_coupling_exact(gmm_plan plan, const double* Q, int q_complex) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  if (!Q) {
+    if (plan->cpl_exact) {
+      plan->cpl_exact = false;
+      plan->E_dz = std::nan("");
+    }
+    return GMM_OK;
+  }
+  if (q_complex != 0 && q_complex != 1) return fail(GMM_ERR_ARG, "q_complex must be 0 or 1");
+  const int N = plan->N;
+  if (N > gmm::kGainNmax) return fail(GMM_ERR_UNSUPPORTED, "linear coupling supports up to 22 modes");
+  if (plan->gain_on)
+    return fail(GMM_ERR_UNSUPPORTED, "the gain term with the coupling in the linear operator is not implemented");
+  try {
+    std::vector<std::complex<double>> Qc((size_t)N * N);
+    double qmax = 0.0;
+    for (size_t i = 0; i < Qc.size(); ++i) {
+      const double re = q_complex ? Q[2 * i] : Q[i], im = q_complex ? Q[2 * i + 1] : 0.0;
+      if (!std::isfinite(re) || !std::isfinite(im)) return fail(GMM_ERR_ARG, "non-finite coupling coefficient");
+      Qc[i] = {re, im};
+      qmax = std::max(qmax, std::abs(Qc[i]));
+    }
+    for (int n = 0; n < N; ++n)
+      for (int p = 0; p < N; ++p)
+        if (std::abs(Qc[(size_t)n * N + p] - std::conj(Qc[(size_t)p * N + n])) > 1e-12 * qmax)
+          return fail(GMM_ERR_ARG, "the coupling in the linear operator needs a Hermitian Q (Q_np = conj(Q_pn))");
+    std::vector<double> lam;
+    std::vector<std::complex<double>> U;
+    coupled_eigen(plan, Qc, lam, U);
+    const size_t nU = (size_t)N * N * plan->nt;
+    if (!plan->Uc && (dev_alloc(&plan->const_bytes, &plan->Uc, nU * 2 * plan->esz) ||
+                      dev_alloc(&plan->const_bytes, &plan->lam, lam.size() * sizeof(double))))
+      return GMM_ERR_NOMEM;
+    hipError_t e;
+    if (plan->fp64) {
+      std::vector<cplx<double>> u(nU);
+      for (size_t i = 0; i < nU; ++i) u[i] = {U[i].real(), U[i].imag()};
+      e = hipMemcpy(plan->Uc, u.data(), nU * sizeof(cplx<double>), hipMemcpyHostToDevice);
+    } else {
+      std::vector<cplx<float>> u(nU);
+      for (size_t i = 0; i < nU; ++i) u[i] = {(float)U[i].real(), (float)U[i].imag()};
+      e = hipMemcpy(plan->Uc, u.data(), nU * sizeof(cplx<float>), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess || hipMemcpy(plan->lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice) !=
+                               hipSuccess)
+      return fail(GMM_ERR_HIP, "copy of the coupled-operator eigenvectors failed");
+  } catch (const std::bad_alloc&) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+  plan->coupling_on = false;  // one placement of the coupling at a time
+  plan->cpl_exact = true;
+  plan->E_dz = std::nan("");
   g_last_error.clear();
   return GMM_OK;
 }

@@ -29,7 +29,7 @@ GMM_FP32 = 1
 GMM_BF16X3 = 2
 
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_plan_set_gain",
-           "gmm_plan_set_coupling", "gmm_nonlinear",
+           "gmm_plan_set_coupling", "gmm_plan_set_coupling_exact", "gmm_nonlinear",
            "gmm_plan_destroy", "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable",
            "gmm_profile_read")
 PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project",
@@ -78,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_plan_set_gain.restype = ci
     lib.gmm_plan_set_coupling.argtypes = [vp, vp, ci]
     lib.gmm_plan_set_coupling.restype = ci
+    lib.gmm_plan_set_coupling_exact.argtypes = [vp, vp, ci]
+    lib.gmm_plan_set_coupling_exact.restype = ci
     lib.gmm_nonlinear.argtypes = [vp, vp, ci, vp]
     lib.gmm_nonlinear.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
@@ -217,6 +219,18 @@ class Plan:
                                  .reshape(self.n_modes, self.n_modes))
         self._coupling = Q
         _check(self.lib.gmm_plan_set_coupling(self.handle, _host_ptr(Q), cplx_q))
+
+    def set_coupling_exact(self, Q=None):
+        """The same coupling placed in the linear operator (exact for any step): Q [N][N] Hermitian,
+        Q[n, p] = conj(Q[p, n]), or None to turn it off."""
+        if Q is None:
+            _check(self.lib.gmm_plan_set_coupling_exact(self.handle, None, 0))
+            return
+        cplx_q = int(np.iscomplexobj(Q))
+        Q = np.ascontiguousarray(np.asarray(Q, dtype=np.complex128 if cplx_q else np.float64)
+                                 .reshape(self.n_modes, self.n_modes))
+        self._coupling = Q
+        _check(self.lib.gmm_plan_set_coupling_exact(self.handle, _host_ptr(Q), cplx_q))
 
     def nonlinear(self, At, out=None):
         """Integrand factor of Eq. (MPA_eq) for spectra At [count][N][Nt]."""

@@ -118,6 +118,7 @@ def test_null_arguments(lib):
     assert lib.gmm_propagate_rk4ip(None, None, 1.0, 1.0, None, None) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_plan_set_gain(None, None, 1.0) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_plan_set_coupling(None, None, 0) == gmmpa.GMM_ERR_ARG
+    assert lib.gmm_plan_set_coupling_exact(None, None, 0) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_nonlinear(None, None, 1, None) == gmmpa.GMM_ERR_ARG
     assert lib.gmm_plan_destroy(None) == 0
     assert lib.gmm_plan_device_bytes(None) == 0

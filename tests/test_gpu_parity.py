@@ -509,9 +509,96 @@ def test_two_mode_coupler_on_gpu(torch_gpu):
     assert abs(frac - (k / W) ** 2 * math.sin(W * L) ** 2) < 1e-10
 
 
+# ----------------------------------------------- linear coupling inside the linear operator (Sec. III.F)
+def _hermitian(w, seed=7, scale=60.0):
+    Qh = _coupling(w, seed=seed, scale=scale)
+    return Qh + Qh.conj().T
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", [(2, 256, 0.0, 0, 80e-15), (3, 512, 0.18, 1, 40e-15), (5, 256, 0.18, 1, 80e-15)],
+                         ids=lambda c: f"g{c[0]}_nt{c[1]}_fR{c[2]}_s{c[3]}")
+def test_exact_coupling_mpa_matches_oracle(torch_gpu, prec, case):
+    """Complex Hermitian Q in the linear operator (matrix exponential per
+    frequency; the GPU iterates in the eigenbasis): MPA at fixed iterations,
+    two large steps of 3 small ones plus a shorter one, against the oracle."""
+    torch = torch_gpu
+    g, nt, fR, sh, dt = case
+    w = small_workload(N_groups=g, nt=nt, fR=fR, s=sh, dt=dt)
+    Q = _hermitian(w)
+    m = O.model_from_workload(w)
+    m.Q, m.Q_linear = Q, True
+    L = 7 * w.dz
+    ref = O.mpa_propagate(w.A0, m, L, w.dz, 3, fixed_iters=4)
+    plan = make_plan(w, prec, fixed_iters=4)
+    plan.set_coupling_exact(Q)
+    err = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 3).field.cpu().numpy(), ref)
+    print(f"[{prec} {case}] exact-coupling MPA error {err:.3e}", flush=True)
+    assert err < TOL_PROP[prec]
+
+
+def test_exact_coupling_two_mode_coupler_at_coarse_steps(torch_gpu):
+    """Two modes, Q = [[0, k], [k, 0]], mismatch d, no Kerr: with the coupling in
+    the linear operator the GPU MPA reaches (k / W)^2 sin^2(W L) in 3 steps."""
+    torch = torch_gpu
+    from paper_1708_05324_amd import gmmpa
+    nt, dt, k, d, L = 256, 50e-15, 30.0, 40.0, 0.05
+    t = synth.time_grid(nt, dt)
+    A0 = np.stack([np.exp(-t ** 2 / (2 * (500e-15) ** 2)) + 0j, np.zeros(nt, complex)])
+    betas = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    plan = gmmpa.Plan(betas, np.zeros((2, 2, 2, 2)), None, nt=nt, dt=dt, omega0=synth.GrinFiber().omega0,
+                      n2=0.0, fR=0.0, self_steepening=0, precision="fp64", fixed_iters=2)
+    plan.set_coupling_exact(np.array([[0.0, k], [k, 0.0]]))
+    A = plan.propagate(to_dev(torch, A0, "fp64"), L, L / 3, 3).field.cpu().numpy()
+    W = math.sqrt(k ** 2 + (d / 2) ** 2)
+    frac = float(np.sum(np.abs(A[1]) ** 2) / np.sum(np.abs(A0) ** 2))
+    print(f"coupler fraction {frac:.14f} expected {(k / W) ** 2 * math.sin(W * L) ** 2:.14f}", flush=True)
+    assert abs(frac - (k / W) ** 2 * math.sin(W * L) ** 2) < 1e-12
+
+
+def test_exact_coupling_with_zero_q_is_the_uncoupled_plan(torch_gpu):
+    """Q = 0 in the linear operator: identity eigenvectors, lam = the dispersion
+    phase; the propagation equals the plan without coupling."""
+    torch = torch_gpu
+    w = small_workload(N_groups=2, nt=512, fR=0.18, s=1, dt=40e-15)
+    plan = make_plan(w, "fp64", fixed_iters=3)
+    ref = plan.propagate(to_dev(torch, w.A0, "fp64"), 5 * w.dz, w.dz, 3).field.cpu().numpy()
+    plan.set_coupling_exact(np.zeros((w.n_modes, w.n_modes)))
+    got = plan.propagate(to_dev(torch, w.A0, "fp64"), 5 * w.dz, w.dz, 3).field.cpu().numpy()
+    assert relmax(got, ref) < 1e-12
+
+
+def test_exact_coupling_errors_and_switching(torch_gpu):
+    """A non-Hermitian Q is rejected; the gain term and RK4IP are not combined
+    with it; setting the integrand coupling turns the exact form off (and the
+    propagation then equals the integrand-form oracle)."""
+    torch = torch_gpu
+    from paper_1708_05324_amd import gmmpa
+    w = small_workload(N_groups=2, nt=256, fR=0.0, s=0, dt=80e-15)
+    plan = make_plan(w, "fp64", fixed_iters=3)
+    Qn = _coupling(w)
+    with pytest.raises(gmmpa.GmmError) as e:
+        plan.set_coupling_exact(Qn)
+    assert e.value.code == gmmpa.GMM_ERR_ARG
+    Q = _hermitian(w)
+    plan.set_coupling_exact(Q)
+    with pytest.raises(gmmpa.GmmError) as e:
+        plan.set_gain(np.full(w.n_modes, 1.0), 1.0)
+    assert e.value.code == gmmpa.GMM_ERR_UNSUPPORTED
+    with pytest.raises(gmmpa.GmmError) as e:
+        plan.propagate_rk4ip(to_dev(torch, w.A0, "fp64"), w.dz, w.dz)
+    assert e.value.code == gmmpa.GMM_ERR_UNSUPPORTED
+    plan.set_coupling(Q)
+    m = O.model_from_workload(w)
+    m.Q = Q
+    ref = O.mpa_propagate(w.A0, m, 4 * w.dz, w.dz, 2, fixed_iters=3)
+    got = plan.propagate(to_dev(torch, w.A0, "fp64"), 4 * w.dz, w.dz, 2).field.cpu().numpy()
+    assert relmax(got, ref) < TOL_PROP["fp64"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_general_route_21_modes_with_gain(torch_gpu, prec):
-    """21 modes (the largest group count in this build): general route with a
+    """21 modes (the largest mode count the library takes): general route with a
     complex S^K != S^R (882 output rows, K = 924; the FP64 tile needs more than
     64 KB of LDS) plus the saturating gain, against the oracle."""
     torch = torch_gpu
