@@ -105,53 +105,93 @@ __global__ __launch_bounds__(256) void k_phase_table_lam(cplx<T>* __restrict__ E
 //   BACK = false: dst_c(w) = U(w) (E_{j0+c}(w) .* src_c(w))     (eigenbasis -> modes)
 //   BACK = true:  dst_c(w) = conj(E_{j0+c}(w)) .* (U(w)^H src_c(w))  (modes -> eigenbasis)
 // E = nullptr: no phase.  src row c at src + c * src_jrows * nt (src_jrows N or
-// 0); dst rows [count][N][nt]; dst may be src.  One block of 256 threads owns W
-// frequencies for every sub-step: the N x N x W tile of U (or U^H) is staged in
-// LDS once, then per sub-step the N x W source tile, and thread (w, g) forms the
-// rows p = g mod (256 / W) of its frequency.
-template <typename T, int W, bool BACK>
+// 0); dst rows [count][N][nt]; dst may be src.
+//
+// One block of 256 threads owns W frequencies for every sub-step, so each
+// frequency's N x N matrix is read once: thread (w, g) keeps the rows
+// p = g mod (256 / W) of its frequency in registers.  Sub-steps go in chunks of
+// kMixChunk: all source loads of a chunk (and, going back, the thread's phase
+// factors) are issued together and staged in LDS, then the products of the
+// chunk run from LDS.
+constexpr int kMixChunk = 12;
+template <typename T>
+constexpr int mix_width() { return 8; }
+template <typename T>
+constexpr size_t mix_lds_bytes(int N) {
+  return (size_t)kMixChunk * N * mix_width<T>() * sizeof(cplx<T>);
+}
+
+template <typename T, bool BACK>
 __global__ __launch_bounds__(256) void k_mode_mix(const cplx<T>* src, long src_jrows, cplx<T>* dst,
                                                   const cplx<T>* __restrict__ U, const cplx<T>* __restrict__ E,
                                                   int j0, int N, int nt, int count, const Ctrl* ctrl) {
-  constexpr int G = 256 / W;
+  constexpr int W = mix_width<T>(), G = 256 / W;
+  constexpr int PMAX = (kGainNmax + G - 1) / G;                      // rows per thread
+  constexpr int SMAX = (kMixChunk * kGainNmax * W + 255) / 256;      // staged elements per thread
   if (skip_iteration(ctrl)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* sU = reinterpret_cast<cplx<T>*>(smem_raw);  // [N][N][W]: M_pq(k0 + w)
-  cplx<T>* sS = sU + N * N * W;                         // [N][W]
+  cplx<T>* sS = reinterpret_cast<cplx<T>*>(smem_raw);  // [kMixChunk][N][W]
   const int tid = threadIdx.x, w = tid % W, g = tid / W;
   const int k0 = blockIdx.x * W;
-  for (int i = tid; i < N * N * W; i += 256) {
-    const int pq = i / W, ww = i - pq * W, p = pq / N, q = pq - p * N;
-    if (BACK) {  // (U^H)_pq = conj(U_qp)
-      const cplx<T> u = U[((size_t)q * N + p) * nt + k0 + ww];
-      sU[i] = cplx<T>{u.re, -u.im};
-    } else {
-      sU[i] = U[((size_t)p * N + q) * nt + k0 + ww];
-    }
+  // rows p = g + G r of this frequency's matrix, straight from global memory (all loads in flight at once;
+  // the W threads of a row read W consecutive frequencies): M = U, or U^H with (U^H)_pq = conj(U_qp)
+  cplx<T> m[PMAX][kGainNmax];
+#pragma unroll
+  for (int r = 0; r < PMAX; ++r) {
+    const int p = g + G * r;
+#pragma unroll
+    for (int q = 0; q < kGainNmax; ++q)
+      if (p < N && q < N) {
+        const cplx<T> u = BACK ? U[((size_t)q * N + p) * nt + k0 + w] : U[((size_t)p * N + q) * nt + k0 + w];
+        m[r][q] = BACK ? cplx<T>{u.re, -u.im} : u;
+      }
   }
-  for (int c = 0; c < count; ++c) {
-    __syncthreads();  // the previous sub-step's products are done with sS
-    for (int i = tid; i < N * W; i += 256) {
-      const int q = i / W, ww = i - q * W;
-      const size_t k = (size_t)k0 + ww;
-      cplx<T> v = src[((size_t)c * src_jrows + q) * nt + k];
-      if (!BACK && E != nullptr) v = cmul(v, E[((size_t)(j0 + c) * N + q) * nt + k]);
-      sS[i] = v;
+  for (int c0 = 0; c0 < count; c0 += kMixChunk) {
+    const int nc = min(kMixChunk, count - c0);
+    cplx<T> ph[PMAX][kMixChunk];
+    if (BACK && E != nullptr) {
+#pragma unroll
+      for (int r = 0; r < PMAX; ++r)
+#pragma unroll
+        for (int cc = 0; cc < kMixChunk; ++cc) {
+          const int p = g + G * r;
+          if (p < N && cc < nc) ph[r][cc] = E[((size_t)(j0 + c0 + cc) * N + p) * nt + k0 + w];
+        }
+    }
+    __syncthreads();  // the previous chunk's products are done with sS
+#pragma unroll
+    for (int u = 0; u < SMAX; ++u) {
+      const int i = tid + 256 * u;  // element (cc, q, ww) of the chunk
+      if (i < nc * N * W) {
+        const int cq = i / W, ww = i - cq * W, cc = cq / N, q = cq - cc * N;
+        const size_t k = (size_t)k0 + ww;
+        cplx<T> v = src[((size_t)(c0 + cc) * src_jrows + q) * nt + k];
+        if (!BACK && E != nullptr) v = cmul(v, E[((size_t)(j0 + c0 + cc) * N + q) * nt + k]);
+        sS[i] = v;
+      }
     }
     __syncthreads();
-    for (int p = g; p < N; p += G) {
-      cplx<T> acc{T(0), T(0)};
-      for (int q = 0; q < N; ++q) {
-        const cplx<T> m = sU[(p * N + q) * W + w], x = sS[q * W + w];
-        acc.re += m.re * x.re - m.im * x.im;
-        acc.im += m.re * x.im + m.im * x.re;
+#pragma unroll
+    for (int r = 0; r < PMAX; ++r) {
+      const int p = g + G * r;
+      if (p >= N) continue;
+      for (int cc = 0; cc < nc; ++cc) {
+        cplx<T> acc{T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < kGainNmax; ++q) {
+          if (q < N) {
+            const cplx<T> x = sS[(cc * N + q) * W + w];
+            acc.re += m[r][q].re * x.re - m[r][q].im * x.im;
+            acc.im += m[r][q].re * x.im + m[r][q].im * x.re;
+          }
+        }
+        if (BACK && E != nullptr) {
+#pragma unroll
+          for (int c2 = 0; c2 < kMixChunk; ++c2)
+            if (c2 == cc) acc = cmul(acc, cplx<T>{ph[r][c2].re, -ph[r][c2].im});
+        }
+        dst[((size_t)(c0 + cc) * N + p) * nt + k0 + w] = acc;
       }
-      const size_t o = ((size_t)c * N + p) * nt + k0 + w;
-      if (BACK && E != nullptr) {
-        const cplx<T> e = E[((size_t)(j0 + c) * N + p) * nt + k0 + w];
-        acc = cmul(acc, cplx<T>{e.re, -e.im});
-      }
-      dst[o] = acc;
     }
   }
 }

@@ -69,22 +69,22 @@ hipError_t Launch<T>::phase_table_lam(cplx<T>* E, const double* lam, int N, int 
 template <typename T>
 hipError_t Launch<T>::mode_mix(bool back, const cplx<T>* src, long src_jrows, cplx<T>* dst, const cplx<T>* U,
                                const cplx<T>* E, int j0, int N, int nt, int count, const Ctrl* ctrl, hipStream_t s) {
-  constexpr int W = sizeof(T) == 4 ? 32 : 16;  // frequencies per block
+  constexpr int W = mix_width<T>();  // frequencies per block
   if (N < 1 || N > kGainNmax || nt % W || count < 1) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(N * N + N) * W * sizeof(cplx<T>);
-  const int lds_max = (int)((size_t)(kGainNmax * kGainNmax + kGainNmax) * W * sizeof(cplx<T>));
+  const size_t lds = mix_lds_bytes<T>(N);
+  const int lds_max = (int)mix_lds_bytes<T>(kGainNmax);
   if (back) {
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, W, true>,
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, true>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_mode_mix<T, W, true>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N, nt,
+    hipLaunchKernelGGL((k_mode_mix<T, true>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N, nt,
                        count, ctrl);
   } else {
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, W, false>,
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_mode_mix<T, false>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_mode_mix<T, W, false>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N,
-                       nt, count, ctrl);
+    hipLaunchKernelGGL((k_mode_mix<T, false>), dim3(nt / W), dim3(256), lds, s, src, src_jrows, dst, U, E, j0, N, nt,
+                       count, ctrl);
   }
   return hipGetLastError();
 }
