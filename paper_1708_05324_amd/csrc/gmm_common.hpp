@@ -19,6 +19,8 @@ struct Ctrl {
 // Most modes the saturating-gain kernels take (their N x N matrices sit in LDS),
 // and the samples per partial sum of the pair integrals.
 constexpr int kGainNmax = 22;
+// Segment length (log2) of the overlap-save Raman convolution.
+constexpr int kOsLogF = 11;
 constexpr int kGainChunkHost = 128;
 // Partial sums per sub-step of the pair integrals: 64 (or Nt / 128 for short windows).
 inline int gain_partials(int nt) { return nt / kGainChunkHost < 64 ? nt / kGainChunkHost : 64; }

@@ -364,6 +364,22 @@ hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const fl
   return launch_dense_bf16_nrb<kDenseRB>(Ghi, Glo, Bd, A_NL, N, KD, KD32, Nt, count, ctrl, s);
 }
 
+hipError_t launch_conv_os(const float* Y, float* Yout, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
+                          int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf, const Ctrl* ctrl,
+                          hipStream_t s) {
+  using S = FftShape<kOsLogF, 4, 4>;
+  if (Lh < 1 || V < 1 || Lh - 1 + V > S::N || Nt < S::N || (Nt & (Nt - 1))) return hipErrorInvalidValue;
+  const int nseg = (Nt + V - 1) / V, total = nseg * ((R + 1) / 2) * count;
+  const dim3 grid(8 * ((total + 7) / 8));
+  if (Bhi != nullptr)
+    hipLaunchKernelGGL((k_conv_os<float, true>), grid, dim3(S::THREADS), 0, s, Y, nullptr, Bhi, Blo, R, RQ, count, 32,
+                       Nt, Lh, V, nseg, Gf, twf, ctrl);
+  else
+    hipLaunchKernelGGL((k_conv_os<float, false>), grid, dim3(S::THREADS), 0, s, Y, Yout, nullptr, nullptr, R, RQ,
+                       count, 32, Nt, Lh, V, nseg, Gf, twf, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
   using T = float;

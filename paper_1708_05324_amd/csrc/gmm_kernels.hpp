@@ -1147,6 +1147,62 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF1
   }
 }
 
+// k_conv_os: the same filtering by overlap-save, for a Raman response whose
+// normalised weights w_j have decayed below a small tail after Lh samples
+// (the plan checks the tail): with the truncated kernel
+//   g_j = (1 - fR) delta_j0 + fR w_j,  j < Lh,
+// the circular convolution of a row is, per output segment [t0, t0 + V), the
+// valid part of a 2^kOsLogF-point circular convolution of the input samples
+// t0 - (Lh - 1) .. (indices mod Nt).  Gf = DFT_{+}(g padded) / F, twf the
+// F-point twiddles.  One block of FftShape<kOsLogF> threads per (segment, row
+// pair, sub-step), XCD-local order with the segments of a row adjacent; two real
+// rows are one complex transform, as in k_conv; same outputs as k_conv.
+template <typename T, bool BF16OUT>
+__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS)) void k_conv_os(
+    const T* __restrict__ Y, T* __restrict__ Yout, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo, int R,
+    int RQ, int count, int KW, int Nt, int Lh, int V, int nseg, const cplx<T>* __restrict__ Gf,
+    const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
+  using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int PB = (R + 1) / 2;
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * PB * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x;
+  const int rowpair = w / nseg, seg = w - rowpair * nseg;
+  const int jj = rowpair / PB, r1 = 2 * (rowpair - jj * PB);
+  const T* y1 = Y + ((size_t)jj * RQ + r1) * Nt;
+  const T* y2 = y1 + Nt;  // row r1 + 1 < RQ (rows up to RQ are allocated; beyond r they are zero)
+  const int t0 = seg * V, base = t0 - (Lh - 1);
+  cplx<T> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = (base + tid + i * S::THREADS) & (Nt - 1);
+    z[i] = {y1[t], y2[t]};
+  }
+  block_fft<S, T, +1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gf[tid + i * S::THREADS]);
+  block_fft<S, T, -1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int o = tid + i * S::THREADS - (Lh - 1);
+    const int t = t0 + o;
+    if (o < 0 || o >= V || t >= Nt) continue;
+    if constexpr (BF16OUT) {
+      uint32_t h, l;
+      bf16_split2((float)z[i].re, (float)z[i].im, h, l);
+      const size_t at = ((size_t)jj * KW + (r1 >> 1)) * Nt + t;
+      Bhi[at] = h;
+      Blo[at] = l;
+    } else {
+      T* o1 = Yout + ((size_t)jj * RQ + r1) * Nt;
+      o1[t] = z[i].re;
+      o1[Nt + t] = z[i].im;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // General-tensor route (S^K != S^R, complex S, or S without the (m, n) and
 // (p, l) symmetries, e.g. polarised modes).  With B_mn = A_m A_n^* Hermitian in

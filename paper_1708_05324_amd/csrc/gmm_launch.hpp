@@ -84,6 +84,11 @@ hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, cons
 constexpr int kDenseGRows = 464;
 hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const float* Bd, cplx<float>* A_NL, int N,
                                       int KD, int KD32, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+// Overlap-save form of the rank-r convolution (complex64 fields): Lh kernel taps, V outputs per segment,
+// Gf / twf the segment filter and twiddles (2^11 points); Bhi == nullptr: FP32 output rows in Yout.
+hipError_t launch_conv_os(const float* Y, float* Yout, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
+                          int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf, const Ctrl* ctrl,
+                          hipStream_t s);
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 

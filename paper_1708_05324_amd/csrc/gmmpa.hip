@@ -160,6 +160,10 @@ struct gmm_plan_s {
   void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
   void* Vlo = nullptr;
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
+  // overlap-save form of the rank-r convolution (FP32 / BF16X3 plans, short Raman response)
+  int os_lh = 0, os_v = 0;  // kernel taps, outputs per 2^11-point segment (0: full-row transforms)
+  void* Gos = nullptr;      // [2^11] segment filter DFT_{+}(g) / 2^11, complex64
+  void* twos = nullptr;     // [2^11] exp(-2 pi i m / 2^11), complex64
   // general-tensor route (S^R != S^K, complex S, or S without the packed symmetries)
   bool dense = false;
   int KD = 0, rows_pad = 0;  // real pair rows per sub-step (multiple of 4); output rows 2 N^2 padded to 64
@@ -355,15 +359,30 @@ struct Runner {
         if (P->bf16) {
           uint32_t* bhi = (uint32_t*)P->Bp;
           uint32_t* blo = bhi + bp_plane_words(P);
-          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
-                                                              (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
+          if (P->os_lh)
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, nullptr, bhi, blo, R, P->rq, count, P->nt, P->os_lh,
+                                                              P->os_v, (const cplx<float>*)P->Gos,
+                                                              (const cplx<float>*)P->twos, ctrl, P->stream));
+          else
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
+                                                                (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
                                                                      P->N, R, P->nt, count, ctrl, P->stream));
         }
       }
       if (!P->bf16) {
-        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
-                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
+        bool os_done = false;
+        if constexpr (std::is_same<T, float>::value) {
+          if (P->os_lh) {
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, (float*)P->Bp, nullptr, nullptr, R, P->rq, count,
+                                                              P->nt, P->os_lh, P->os_v, (const cplx<float>*)P->Gos,
+                                                              (const cplx<float>*)P->twos, ctrl, P->stream));
+            os_done = true;
+          }
+        }
+        if (!os_done)
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
+                                                        (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
         if constexpr (std::is_same<T, float>::value) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, P->Bp, nullptr,
                                                                      W, P->N, P->rq, P->nt, count, ctrl, P->stream));
@@ -975,12 +994,53 @@ int build_raman(gmm_plan_s* P, const double* hR, double blend) {
   return GMM_OK;
 }
 
+// Overlap-save filter of the rank-r route (FP32 / BF16X3 plans): the normalised
+// weights w_k of h_R are cut after the first Lh samples once the absolute sum of
+// everything beyond (the causal tail and the wrapped samples near Nt) is at most
+// kOsTail of their absolute sum, far below the field precision.  Segments of
+// F = 2^11 points then give V = F - Lh + 1 outputs each.  Used for Nt >= 2^13
+// and Lh <= F / 2 (at least half of each segment is output); otherwise the plan
+// keeps the full-row transforms.
+constexpr double kOsTail = 1e-9;
+
+int build_overlap_save(gmm_plan_s* P, const double* hR, double blend) {
+  constexpr int F = 1 << gmm::kOsLogF;
+  const int n = P->nt;
+  if (n < 8192) return GMM_OK;
+  double sum = 0.0, asum = 0.0;
+  for (int k = 0; k < n; ++k) sum += hR[k];
+  for (int k = 0; k < n; ++k) asum += std::fabs(hR[k] / sum);
+  int lh = n;
+  double tail = 0.0;
+  while (lh > 1 && tail + std::fabs(hR[lh - 1] / sum) <= kOsTail * asum) tail += std::fabs(hR[--lh] / sum);
+  if (lh > F / 2) return GMM_OK;
+  std::vector<std::complex<double>> g(F, 0.0);
+  for (int k = 0; k < lh; ++k) g[k] = blend * hR[k] / sum;
+  g[0] += 1.0 - blend;
+  host_fft_plus(g);
+  std::vector<cplx<float>> gf(F), tf(F);
+  for (int k = 0; k < F; ++k) {
+    gf[k] = cplx<float>{(float)(g[k].real() / F), (float)(g[k].imag() / F)};
+    const std::complex<double> t = std::polar(1.0, -2.0 * kPi * (double)k / F);
+    tf[k] = cplx<float>{(float)t.real(), (float)t.imag()};
+  }
+  int rc;
+  if ((rc = dev_alloc(&P->const_bytes, &P->Gos, F * sizeof(cplx<float>))) ||
+      (rc = dev_alloc(&P->const_bytes, &P->twos, F * sizeof(cplx<float>))))
+    return rc;
+  GMM_HIP(hipMemcpy(P->Gos, gf.data(), F * sizeof(cplx<float>), hipMemcpyHostToDevice));
+  GMM_HIP(hipMemcpy(P->twos, tf.data(), F * sizeof(cplx<float>), hipMemcpyHostToDevice));
+  P->os_lh = lh;
+  P->os_v = F - lh + 1;
+  return GMM_OK;
+}
+
 void destroy(gmm_plan_s* P) {
   if (!P) return;
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
                   P->G, P->Ghi, P->Glo, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
-                  P->Uc, (void*)P->lam,
+                  P->Uc, (void*)P->lam, P->Gos, P->twos,
                   (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
@@ -1144,6 +1204,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     if (!dense && p->factor_policy == 0) {
       rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
+      if (P->factored && !fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
     }
   }
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
