@@ -302,24 +302,29 @@ struct Runner {
   // psi_c starts at psi + c * jrows * Nt: jrows = N (one field per sub-step)
   // or 0 (every sub-step reads the same field).  Field rows go through
   // `work`; `out` may be `work` itself.
-  int eval(const cplx<T>* psi, long jrows, int count, int j0, double dz, cplx<T>* out, const Ctrl* ctrl) {
+  // part 0: the whole evaluation; part 1: its first half (transforms to time, gain matrices, pair rows or
+  // Y = V B and the Raman convolution); part 2: the rest (contraction, transforms back, gain term).  The MPA
+  // driver queues the halves separately so that it can wait for a stop flag in the middle of an iteration.
+  int eval(const cplx<T>* psi, long jrows, int count, int j0, double dz, cplx<T>* out, const Ctrl* ctrl,
+           int part = 0) {
+    const bool doA = part != 2, doB = part != 1;
     if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
     if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
     cplx<T>* W = (cplx<T>*)P->work;
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
     // coupled linear operator: psi is in the eigenbasis; the modes are U (exp(i lam z) psi)
     const bool mix = P->cpl_exact && E != nullptr;
-    if (mix) {
+    if (mix && doA) {
       GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::mode_mix(false, psi, jrows, W, (const cplx<T>*)P->Uc, E, j0, P->N,
                                                       P->nt, count, ctrl, P->stream));
       GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, W, P->N, W, nullptr, P->N, count, j0, tw(),
                                                            ctrl, P->stream));
-    } else {
+    } else if (doA) {
       GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
                                                            P->stream));
     }
     const bool linear_terms = P->gain_on || P->coupling_on;
-    if (linear_terms) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
+    if (linear_terms && doA) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
       if (count > P->gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
       if (P->gain_on && P->inv_Isat != 0.0)
         GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
@@ -329,28 +334,30 @@ struct Runner {
                                          P->coupling_on ? P->Kc : nullptr, P->Mg, P->N, count, ctrl, P->stream));
     }
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
-      GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
+      if (doA)
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
                                                            count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
                                                            P->stream));
       bool done = false;
       if constexpr (std::is_same<T, float>::value) {
-        if (P->bf16) {
+        if (P->bf16 && doB) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT,
                      gmm::launch_contract_dense_bf16(P->Ghi, P->Glo, (const float*)P->Bp, W, P->N, P->KD, P->KD32,
                                                      P->nt, count, ctrl, P->stream));
-          done = true;
         }
+        done = P->bf16;
       }
-      if (!done)
+      if (!done && doB)
         GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)P->Bp, W, P->N, P->KD,
                                                                    P->rows_pad, P->nt, count, ctrl, P->stream));
     } else if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
       T* Y = (T*)P->Y;
       if constexpr (std::is_same<T, float>::value) {
-        GMM_LAUNCH(P, GMM_PROF_PROJECT,
-                   gmm::launch_project_cols(P->rq, P->kp, P->bf16, P->bf16 ? P->Vhi : P->VT, P->Vlo, W, Y, P->N,
+        if (doA)
+          GMM_LAUNCH(P, GMM_PROF_PROJECT,
+                     gmm::launch_project_cols(P->rq, P->kp, P->bf16, P->bf16 ? P->Vhi : P->VT, P->Vlo, W, Y, P->N,
                                             P->nt, count, ctrl, P->stream));
-      } else {
+      } else if (doA) {
         GMM_LAUNCH(P, GMM_PROF_PROJECT, Launch<T>::project(P->rq, P->kp, (const T*)P->VT, W, Y, P->pairs, P->N,
                                                          P->Np, P->nt, count, ctrl, P->stream));
       }
@@ -359,14 +366,15 @@ struct Runner {
         if (P->bf16) {
           uint32_t* bhi = (uint32_t*)P->Bp;
           uint32_t* blo = bhi + bp_plane_words(P);
-          if (P->os_lh)
+          if (P->os_lh && doA)
             GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, nullptr, bhi, blo, R, P->rq, count, P->nt, P->os_lh,
                                                               P->os_v, (const cplx<float>*)P->Gos,
                                                               (const cplx<float>*)P->twos, ctrl, P->stream));
-          else
+          else if (doA)
             GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_bf16(P->logn, Y, bhi, blo, R, P->rq, count,
                                                                 (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
-          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
+          if (doB)
+            GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
                                                                      P->N, R, P->nt, count, ctrl, P->stream));
         }
       }
@@ -374,19 +382,21 @@ struct Runner {
         bool os_done = false;
         if constexpr (std::is_same<T, float>::value) {
           if (P->os_lh) {
-            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, (float*)P->Bp, nullptr, nullptr, R, P->rq, count,
+            if (doA)
+              GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, (float*)P->Bp, nullptr, nullptr, R, P->rq, count,
                                                               P->nt, P->os_lh, P->os_v, (const cplx<float>*)P->Gos,
                                                               (const cplx<float>*)P->twos, ctrl, P->stream));
             os_done = true;
           }
         }
-        if (!os_done)
+        if (!os_done && doA)
           GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
                                                         (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
         if constexpr (std::is_same<T, float>::value) {
-          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, P->Bp, nullptr,
+          if (doB)
+            GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, P->Bp, nullptr,
                                                                      W, P->N, P->rq, P->nt, count, ctrl, P->stream));
-        } else {
+        } else if (doB) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)P->Bp, W,
                                                                P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream));
         }
@@ -395,18 +405,23 @@ struct Runner {
       if (P->bf16) {  // packed route, BF16 split
         uint32_t* bhi = (uint32_t*)P->Bp;
         uint32_t* blo = bhi + bp_plane_words(P);
-        GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
+        if (doA)
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
                                                              count, (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
-        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, 128, P->Shi, P->Slo, bhi, blo, W, P->pidx,
+        if (doB)
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_bf16(P->rt, 128, P->Shi, P->Slo, bhi, blo, W, P->pidx,
                                                                    P->N, P->nt, count, ctrl, P->stream));
       }
     }
     if (!P->bf16 && !P->factored && !P->dense) {
-      GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
+      if (doA)
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
-      GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
+      if (doB)
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
                                                            P->N, P->Np, P->nt, count, ctrl, P->stream));
     }
+    if (!doB) return GMM_OK;
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, mix ? nullptr : E, P->N, count, j0,
                                                            P->domega, P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
                                                            P->prm.self_steepening, tw(), ctrl, P->stream));
@@ -422,12 +437,13 @@ struct Runner {
   // One iteration over the m sub-steps of a large step.  The first iteration
   // also evaluates I_0 = N~[A(z0)] in the same launches (sub-step 0, no phase),
   // since every sub-step then reads psi_0; its trapezoid copies I_0 aside.
-  int iteration(int m, double dz, bool first) {
+  // part 0: the whole iteration; 1: the first half of the evaluation; 2: the rest, the trapezoid and the norm.
+  int iteration(int m, double dz, bool first, int part = 0) {
     const long nn = (long)P->N * P->nt;
     cplx<T>* W = (cplx<T>*)P->work;
-    int rc = first ? eval((const cplx<T>*)P->psi0, 0, m + 1, 0, dz, W, P->ctrl)
-                   : eval((const cplx<T>*)P->psi, P->N, m, 1, dz, W, P->ctrl);
-    if (rc) return rc;
+    int rc = first ? eval((const cplx<T>*)P->psi0, 0, m + 1, 0, dz, W, P->ctrl, part)
+                   : eval((const cplx<T>*)P->psi, P->N, m, 1, dz, W, P->ctrl, part);
+    if (rc || part == 1) return rc;
     const cplx<T>* I0 = first ? W : (const cplx<T>*)P->I0;
     const cplx<T>* I = first ? W + nn : W;
     GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
@@ -513,30 +529,30 @@ struct Runner {
         GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
         GMM_HIP(hipStreamSynchronize(P->stream));
       } else {
-        // Queue two iterations, then keep one speculative iteration in flight
-        // while the host reads the flag of the previous one; a queued
-        // iteration after convergence exits at once (device-side guard).
+        // Queue the first iteration and the first half of the second; then, per
+        // iteration n: wait for the flag read after iteration n's norm while the
+        // GPU runs the first half of iteration n + 1, and queue its second half
+        // and the first half of iteration n + 2 only if not converged.  After
+        // convergence only one half-iteration is queued for nothing, and its
+        // launches exit at once (device-side guard).
         P->prof.cur_iter = 1;
         if ((rc = iteration(m, dz, true))) return rc;
         n_enq = 1;
-        if (P->prm.max_iter > 1) {
-          P->prof.cur_iter = 2;
-          if ((rc = iteration(m, dz, false))) return rc;
-          n_enq = 2;
-        }
         for (;;) {
           GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
           hipEvent_t ev;
           GMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
           GMM_HIP(hipEventRecord(ev, P->stream));
-          if (n_enq < P->prm.max_iter) {
+          const bool more = n_enq < P->prm.max_iter;
+          if (more) {
             P->prof.cur_iter = n_enq + 1;
-            if ((rc = iteration(m, dz, false))) { (void)hipEventDestroy(ev); return rc; }
-            ++n_enq;
+            if ((rc = iteration(m, dz, false, 1))) { (void)hipEventDestroy(ev); return rc; }
           }
           GMM_HIP(hipEventSynchronize(ev));
           GMM_HIP(hipEventDestroy(ev));
-          if (P->h_ctrl->done) break;
+          if (P->h_ctrl->done || !more) break;
+          if ((rc = iteration(m, dz, false, 2))) return rc;
+          ++n_enq;
         }
       }
       const Ctrl c = *P->h_ctrl;
