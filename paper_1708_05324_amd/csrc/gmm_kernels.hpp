@@ -1158,7 +1158,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF1
 // pair, sub-step), XCD-local order with the segments of a row adjacent; two real
 // rows are one complex transform, as in k_conv; same outputs as k_conv.
 template <typename T, bool BF16OUT>
-__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS)) void k_conv_os(
+__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), 5) void k_conv_os(
     const T* __restrict__ Y, T* __restrict__ Yout, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo, int R,
     int RQ, int count, int KW, int Nt, int Lh, int V, int nseg, const cplx<T>* __restrict__ Gf,
     const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
