@@ -537,6 +537,24 @@ def test_exact_coupling_mpa_matches_oracle(torch_gpu, prec, case):
     assert err < TOL_PROP[prec]
 
 
+@pytest.mark.parametrize("prec,groups", [("fp32", 3), ("fp64", 6)], ids=["general_6_modes_fp32", "general_21_modes_fp64"])
+def test_exact_coupling_with_general_tensors(torch_gpu, prec, groups):
+    """The coupling in the linear operator on the general-tensor route (complex
+    S^K != S^R), up to 21 modes (the widest mode mixing), MPA against the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=groups, nt=256, fR=0.18, s=1, dt=80e-15)
+    m, SK, SR = _general_model(w, True, True, seed=12)
+    Q = _hermitian(w, seed=13)
+    m.Q, m.Q_linear = Q, True
+    L = 4 * w.dz
+    ref = O.mpa_propagate(w.A0, m, L, w.dz, 2, fixed_iters=3)
+    plan = _general_plan(w, SK, SR, prec, fixed_iters=3)
+    plan.set_coupling_exact(Q)
+    err = relmax(plan.propagate(to_dev(torch, w.A0, prec), L, w.dz, 2).field.cpu().numpy(), ref)
+    print(f"[{prec} {w.n_modes} modes] exact coupling, general route: {err:.3e}", flush=True)
+    assert err < TOL_PROP[prec]
+
+
 def test_exact_coupling_two_mode_coupler_at_coarse_steps(torch_gpu):
     """Two modes, Q = [[0, k], [k, 0]], mismatch d, no Kerr: with the coupling in
     the linear operator the GPU MPA reaches (k / W)^2 sin^2(W L) in 3 steps."""
