@@ -380,6 +380,23 @@ hipError_t launch_conv_os(const float* Y, float* Yout, uint32_t* Bhi, uint32_t* 
   return hipGetLastError();
 }
 
+hipError_t launch_pairs_os(const cplx<float>* A, float* Bp, uint32_t* Bhi, uint32_t* Blo, const int2* pairs, int N,
+                           int Np, int count, int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf,
+                           const Ctrl* ctrl, hipStream_t s) {
+  using S = FftShape<kOsLogF, 4, 4>;
+  if (Lh < 1 || V < 1 || Lh - 1 + V > S::N || Nt < S::N || (Nt & (Nt - 1)) || (Bhi != nullptr && Np > kBf16Kpad))
+    return hipErrorInvalidValue;
+  const int nseg = (Nt + V - 1) / V, total = nseg * ((Np + 1) / 2) * count;
+  const dim3 grid(8 * ((total + 7) / 8));
+  if (Bhi != nullptr)
+    hipLaunchKernelGGL((k_pairs_os<true>), grid, dim3(S::THREADS), 0, s, A, nullptr, Bhi, Blo, pairs, N, Np, count,
+                       kBf16Kpad / 8, Nt, Lh, V, nseg, Gf, twf, ctrl);
+  else
+    hipLaunchKernelGGL((k_pairs_os<false>), grid, dim3(S::THREADS), 0, s, A, Bp, nullptr, nullptr, pairs, N, Np, count,
+                       kBf16Kpad / 8, Nt, Lh, V, nseg, Gf, twf, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
   using T = float;

@@ -1203,6 +1203,71 @@ __global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), 5)
   }
 }
 
+// k_pairs_os: the packed routes' pair products and Raman convolution by the
+// same overlap-save segments (short h_R, complex64 fields): each block forms
+// B_Q1 + i B_Q2 for the input samples of its segment (indices mod Nt) straight
+// from the fields, filters the segment and writes its valid outputs in the
+// layout of k_pairs (BF16OUT = false: rows [count][Np][Nt]) or of k_pairs_bf16
+// (hi/lo planes [count][KB][Nt][8]).
+template <bool BF16OUT>
+__global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS), 5) void k_pairs_os(
+    const cplx<float>* __restrict__ A, float* __restrict__ Bp, uint32_t* __restrict__ Bhi,
+    uint32_t* __restrict__ Blo, const int2* __restrict__ pairs, int N, int Np, int count, int KB, int Nt, int Lh,
+    int V, int nseg, const cplx<float>* __restrict__ Gf, const cplx<float>* __restrict__ twf, const Ctrl* ctrl) {
+  using S = FftShape<kOsLogF, 4, 4>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ float lds[S::LDS_ELEMS];
+  const int PB = (Np + 1) / 2;
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * PB * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x;
+  const int blk = w / nseg, seg = w - blk * nseg;
+  const int jj = blk / PB, Q1 = 2 * (blk - jj * PB), Q2 = Q1 + 1;
+  const bool has2 = Q2 < Np;
+  const int2 a = pairs[Q1];
+  const int2 b = has2 ? pairs[Q2] : a;
+  const bool share_m = b.x == a.x, share_n = b.y == a.y;
+  const cplx<float>* Aj = A + (size_t)jj * N * Nt;
+  const cplx<float>* am = Aj + (size_t)a.x * Nt;
+  const cplx<float>* an = Aj + (size_t)a.y * Nt;
+  const cplx<float>* bm = Aj + (size_t)b.x * Nt;
+  const cplx<float>* bn = Aj + (size_t)b.y * Nt;
+  const int t0 = seg * V, base = t0 - (Lh - 1);
+  cplx<float> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = (base + tid + i * S::THREADS) & (Nt - 1);
+    const cplx<float> x = am[t], y = an[t];
+    float b2 = 0.f;
+    if (has2) {
+      const cplx<float> u = share_m ? x : bm[t], v = share_n ? y : bn[t];
+      b2 = u.re * v.re + u.im * v.im;
+    }
+    z[i] = {x.re * y.re + x.im * y.im, b2};
+  }
+  block_fft<S, float, +1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gf[tid + i * S::THREADS]);
+  block_fft<S, float, -1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int o = tid + i * S::THREADS - (Lh - 1);
+    const int t = t0 + o;
+    if (o < 0 || o >= V || t >= Nt) continue;
+    if constexpr (BF16OUT) {
+      uint32_t h, l;
+      bf16_split2(z[i].re, has2 ? z[i].im : 0.f, h, l);
+      const size_t at = (((size_t)jj * KB + (Q1 >> 3)) * Nt) * 4 + ((Q1 & 7) >> 1) + (size_t)t * 4;
+      Bhi[at] = h;
+      Blo[at] = l;
+    } else {
+      float* o1 = Bp + ((size_t)jj * Np + Q1) * Nt;
+      o1[t] = z[i].re;
+      if (has2) o1[Nt + t] = z[i].im;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // General-tensor route (S^K != S^R, complex S, or S without the (m, n) and
 // (p, l) symmetries, e.g. polarised modes).  With B_mn = A_m A_n^* Hermitian in

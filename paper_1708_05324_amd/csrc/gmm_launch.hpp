@@ -89,6 +89,11 @@ hipError_t launch_contract_dense_bf16(const void* Ghi, const void* Glo, const fl
 hipError_t launch_conv_os(const float* Y, float* Yout, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                           int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf, const Ctrl* ctrl,
                           hipStream_t s);
+// Overlap-save form of the packed routes' pair products and convolution (complex64 fields): Bhi == nullptr
+// writes FP32 rows [count][Np][Nt] to Bp, else the BF16 hi/lo planes [count][kBf16Kpad/8][Nt][8].
+hipError_t launch_pairs_os(const cplx<float>* A, float* Bp, uint32_t* Bhi, uint32_t* Blo, const int2* pairs, int N,
+                           int Np, int count, int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf,
+                           const Ctrl* ctrl, hipStream_t s);
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 

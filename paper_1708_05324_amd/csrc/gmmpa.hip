@@ -405,7 +405,11 @@ struct Runner {
       if (P->bf16) {  // packed route, BF16 split
         uint32_t* bhi = (uint32_t*)P->Bp;
         uint32_t* blo = bhi + bp_plane_words(P);
-        if (doA)
+        if (doA && P->os_lh)
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_os(W, nullptr, bhi, blo, P->pairs, P->N, P->Np, count, P->nt,
+                                                             P->os_lh, P->os_v, (const cplx<float>*)P->Gos,
+                                                             (const cplx<float>*)P->twos, ctrl, P->stream));
+        else if (doA)
           GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_bf16(P->logn, P->raman, W, bhi, blo, P->pairs, P->N, P->Np,
                                                              count, (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
         if (doB)
@@ -414,7 +418,18 @@ struct Runner {
       }
     }
     if (!P->bf16 && !P->factored && !P->dense) {
-      if (doA)
+      bool os_done = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (P->os_lh) {
+          if (doA)
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_os(W, (float*)P->Bp, nullptr, nullptr, P->pairs, P->N,
+                                                               P->Np, count, P->nt, P->os_lh, P->os_v,
+                                                               (const cplx<float>*)P->Gos,
+                                                               (const cplx<float>*)P->twos, ctrl, P->stream));
+          os_done = true;
+        }
+      }
+      if (doA && !os_done)
         GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
       if (doB)
@@ -1010,7 +1025,7 @@ int build_raman(gmm_plan_s* P, const double* hR, double blend) {
   return GMM_OK;
 }
 
-// Overlap-save filter of the rank-r route (FP32 / BF16X3 plans): the normalised
+// Overlap-save filter of the packed and rank-r routes (FP32 / BF16X3 plans): the normalised
 // weights w_k of h_R are cut after the first Lh samples once the absolute sum of
 // everything beyond (the causal tail and the wrapped samples near Nt) is at most
 // kOsTail of their absolute sum, far below the field precision.  Segments of
@@ -1220,8 +1235,8 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     if (!dense && p->factor_policy == 0) {
       rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
-      if (P->factored && !fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
     }
+    if (!dense && !fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
   }
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
   if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||

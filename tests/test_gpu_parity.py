@@ -635,19 +635,21 @@ def test_general_route_21_modes_with_gain(torch_gpu, prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("dt", [5e-15, 0.5e-15], ids=["short_response_overlap_save", "long_response_full_rows"])
-def test_raman_convolution_forms_2_to_13(torch_gpu, prec, dt):
-    """15 modes (the rank-45 route), Nt = 2^13, Raman: at 5 fs sampling h_R has decayed
-    below the tail bound within a few hundred samples and the plan convolves by
-    overlap-save on 2^11-point segments; at 0.5 fs it needs more than 1024
-    samples and the plan keeps the full-row transforms.  Both against the
-    oracle's circular convolution, at operator level and over a large step."""
+@pytest.mark.parametrize("groups", [5, 3], ids=["rank45_route", "packed_route"])
+def test_raman_convolution_forms_2_to_13(torch_gpu, prec, dt, groups):
+    """15 modes (the rank-45 route) and 6 modes (the packed route), Nt = 2^13,
+    Raman: at 5 fs sampling h_R has decayed below the tail bound within a few
+    hundred samples and the plan convolves by overlap-save on 2^11-point
+    segments; at 0.5 fs it needs more than 1024 samples and the plan keeps the
+    full-row transforms.  Both against the oracle's circular convolution, at
+    operator level and over a large step."""
     torch = torch_gpu
-    w = small_workload(N_groups=5, nt=2 ** 13, fR=0.18, s=0, dt=dt)
+    w = small_workload(N_groups=groups, nt=2 ** 13, fR=0.18, s=0, dt=dt)
     m = O.model_from_workload(w)
     ops = O._Ops(m, w.nt)
     At = np.stack([O.to_spectrum(w.A0 * (1 + 0.2 * c)) for c in range(2)])
     plan = make_plan(w, prec, fixed_iters=2)
-    assert plan.rank() == 45
+    assert plan.rank() == (45 if groups == 5 else 0)
     e1 = relmax(plan.nonlinear(to_dev(torch, At, prec)).cpu().numpy(), np.stack([ops.N(a) for a in At]))
     ref = O.mpa_propagate(w.A0, m, 2 * w.dz, w.dz, 2, fixed_iters=2)
     e2 = relmax(plan.propagate(to_dev(torch, w.A0, prec), 2 * w.dz, w.dz, 2).field.cpu().numpy(), ref)
