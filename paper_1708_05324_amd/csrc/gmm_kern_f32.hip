@@ -397,6 +397,66 @@ hipError_t launch_pairs_os(const cplx<float>* A, float* Bp, uint32_t* Bhi, uint3
   return hipGetLastError();
 }
 
+// k_pairs_dense_os: k_pairs_dense by overlap-save segments (short h_R,
+// complex64 fields): item (sub-step, pair, segment); the block forms
+// B_mn = A_m A_n^* at its segment's input samples (indices mod Nt), writes the
+// x, y rows at the valid outputs, then filters the segment (Gf = DFT_{+}(w) / F,
+// w the truncated normalised h_R) and writes xr, yr.
+__global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS)) void k_pairs_dense_os(
+    const cplx<float>* __restrict__ A, float* __restrict__ Bd, const int2* __restrict__ pairs, int N, int Np,
+    int count, int KD, int Nt, int Lh, int V, int nseg, const cplx<float>* __restrict__ Gf,
+    const cplx<float>* __restrict__ twf, const Ctrl* ctrl) {
+  using S = FftShape<kOsLogF, 4, 4>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ float lds[S::LDS_ELEMS];
+  const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * Np * count);
+  if (w < 0) return;
+  const int tid = threadIdx.x;
+  const int blk = w / nseg, seg = w - blk * nseg;
+  const int jj = blk / Np, Q = blk - jj * Np;
+  const int2 mn = pairs[Q];
+  const cplx<float>* am = A + ((size_t)jj * N + mn.x) * Nt;
+  const cplx<float>* an = A + ((size_t)jj * N + mn.y) * Nt;
+  float* out = Bd + (size_t)jj * KD * Nt;
+  const int t0 = seg * V, base = t0 - (Lh - 1);
+  cplx<float> z[S::R];
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int t = (base + tid + i * S::THREADS) & (Nt - 1);
+    const cplx<float> x = am[t], y = an[t];
+    z[i] = {x.re * y.re + x.im * y.im, x.im * y.re - x.re * y.im};  // A_m conj(A_n)
+    const int o = tid + i * S::THREADS - (Lh - 1);
+    if (o >= 0 && o < V && t0 + o < Nt) {
+      out[(size_t)Q * Nt + t0 + o] = z[i].re;
+      out[(size_t)(Np + Q) * Nt + t0 + o] = z[i].im;
+    }
+  }
+  block_fft<S, float, +1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gf[tid + i * S::THREADS]);
+  block_fft<S, float, -1>(z, lds, tid, twf);
+#pragma unroll
+  for (int i = 0; i < S::R; ++i) {
+    const int o = tid + i * S::THREADS - (Lh - 1);
+    const int t = t0 + o;
+    if (o < 0 || o >= V || t >= Nt) continue;
+    out[(size_t)(2 * Np + Q) * Nt + t] = z[i].re;
+    out[(size_t)(3 * Np + Q) * Nt + t] = z[i].im;
+  }
+}
+
+hipError_t launch_pairs_dense_os(const cplx<float>* A, float* Bd, const int2* pairs, int N, int Np, int count, int KD,
+                                 int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf,
+                                 const Ctrl* ctrl, hipStream_t s) {
+  using S = FftShape<kOsLogF, 4, 4>;
+  if (Lh < 1 || V < 1 || Lh - 1 + V > S::N || Nt < S::N || (Nt & (Nt - 1)) || KD < 4 * Np) return hipErrorInvalidValue;
+  const int nseg = (Nt + V - 1) / V, total = nseg * Np * count;
+  const dim3 grid(8 * ((total + 7) / 8));
+  hipLaunchKernelGGL(k_pairs_dense_os, grid, dim3(S::THREADS), 0, s, A, Bd, pairs, N, Np, count, KD, Nt, Lh, V, nseg,
+                     Gf, twf, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s) {
   using T = float;

@@ -94,6 +94,10 @@ hipError_t launch_conv_os(const float* Y, float* Yout, uint32_t* Bhi, uint32_t* 
 hipError_t launch_pairs_os(const cplx<float>* A, float* Bp, uint32_t* Bhi, uint32_t* Blo, const int2* pairs, int N,
                            int Np, int count, int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf,
                            const Ctrl* ctrl, hipStream_t s);
+// Overlap-save form of the general route's pair rows with Raman (complex64 fields), rows [count][KD][Nt].
+hipError_t launch_pairs_dense_os(const cplx<float>* A, float* Bd, const int2* pairs, int N, int Np, int count, int KD,
+                                 int Nt, int Lh, int V, const cplx<float>* Gf, const cplx<float>* twf,
+                                 const Ctrl* ctrl, hipStream_t s);
 hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* Blo, int R, int RQ, int count,
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 

@@ -334,7 +334,18 @@ struct Runner {
                                          P->coupling_on ? P->Kc : nullptr, P->Mg, P->N, count, ctrl, P->stream));
     }
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
-      if (doA)
+      bool os_done = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (P->os_lh) {  // Raman on, short h_R: overlap-save segments
+          if (doA)
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_dense_os(W, (float*)P->Bp, P->pairs, P->N, P->Np, count,
+                                                                     P->KD, P->nt, P->os_lh, P->os_v,
+                                                                     (const cplx<float>*)P->Gos,
+                                                                     (const cplx<float>*)P->twos, ctrl, P->stream));
+          os_done = true;
+        }
+      }
+      if (doA && !os_done)
         GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
                                                            count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
                                                            P->stream));
@@ -1025,7 +1036,8 @@ int build_raman(gmm_plan_s* P, const double* hR, double blend) {
   return GMM_OK;
 }
 
-// Overlap-save filter of the packed and rank-r routes (FP32 / BF16X3 plans): the normalised
+// Overlap-save filter of every route with Raman (FP32 / BF16X3 plans; the general route filters with
+// h_R alone, blend = 1): the normalised
 // weights w_k of h_R are cut after the first Lh samples once the absolute sum of
 // everything beyond (the causal tail and the wrapped samples near Nt) is at most
 // kOsTail of their absolute sum, far below the field precision.  Segments of
@@ -1236,7 +1248,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
       rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
     }
-    if (!dense && !fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
+    if (!fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
   }
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
   if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||

@@ -658,6 +658,24 @@ def test_raman_convolution_forms_2_to_13(torch_gpu, prec, dt, groups):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_general_route_overlap_save_2_to_13(torch_gpu, prec):
+    """General route (complex S^K != S^R, 6 modes), Nt = 2^13 at 5 fs: the pair
+    rows x, y and their Raman-filtered xr, yr come from overlap-save segments;
+    operator and one large step against the oracle."""
+    torch = torch_gpu
+    w = small_workload(N_groups=3, nt=2 ** 13, fR=0.18, s=0, dt=5e-15)
+    m, SK, SR = _general_model(w, True, True, seed=21)
+    ops = O._Ops(m, w.nt)
+    At = np.stack([O.to_spectrum(w.A0 * (1 + 0.2 * c)) for c in range(2)])
+    plan = _general_plan(w, SK, SR, prec, fixed_iters=2)
+    e1 = relmax(plan.nonlinear(to_dev(torch, At, prec)).cpu().numpy(), np.stack([ops.N(a) for a in At]))
+    ref = O.mpa_propagate(w.A0, m, 2 * w.dz, w.dz, 2, fixed_iters=2)
+    e2 = relmax(plan.propagate(to_dev(torch, w.A0, prec), 2 * w.dz, w.dz, 2).field.cpu().numpy(), ref)
+    print(f"[{prec}] general route overlap-save: operator {e1:.3e} propagation {e2:.3e}", flush=True)
+    assert e1 < TOL_OP[prec] and e2 < TOL_PROP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_longest_window_2_to_15(torch_gpu, prec):
     """Nt = 2^15 (the longest FP32 row: 32 points per thread, 1024 threads):
     operator of a 3-mode Kerr + Raman + shock plan and one large step, against
