@@ -1475,8 +1475,15 @@ __global__ __launch_bounds__(256) void k_trapz(
 // a9: psi0 <- exp(D_w z_m) * src (element-wise over [N][Nt]); Em = E[m].
 template <typename T>
 __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
-                                                const cplx<T>* __restrict__ Em, long nn) {
+                                                const cplx<T>* __restrict__ Em, long nn, Ctrl* ctrl) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (ctrl != nullptr && e == 0) {  // fresh control block for the next large step (read back before this launch)
+    ctrl->eps = 0.0;
+    ctrl->iters = 0;
+    ctrl->done = 0;
+    ctrl->status = 0;
+    ctrl->pad = 0;
+  }
   if (e >= nn) return;
   dst[e] = cmul(src[e], Em[e]);
 }

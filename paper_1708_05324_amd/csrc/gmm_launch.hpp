@@ -39,7 +39,8 @@ struct Launch {
                                  const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
-  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s);
+  // dst = Em .* src; with ctrl, also resets the control block for the next large step
+  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl, hipStream_t s);
   // General-tensor route: pair rows [count][KD][Nt] (x, y and, with Raman, xr, yr), then C = G B and NL.
   static hipError_t pairs_dense(int logn, bool raman, const cplx<T>* A, T* Bd, const int2* pairs, int N, int Np,
                                 int count, int KD, const cplx<T>* Hr, const cplx<T>* tw, const Ctrl* ctrl,

@@ -238,8 +238,9 @@ hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T
 }
 
 template <typename T>
-hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, hipStream_t s) {
-  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, Em, nn);
+hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, Em, nn, ctrl);
   return hipGetLastError();
 }
 

@@ -543,9 +543,9 @@ struct Runner {
                                   nullptr, 0, P->N, P->nt, 1, nullptr, P->stream));
     long done = 0;
     int status = GMM_OK;
+    GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));  // later large steps: reset by the close launch
     while (done < n_small) {
       const int m = (int)std::min<long>(M, n_small - done);
-      GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));
       int n_enq = 0;
       if (P->prm.fixed_iters > 0) {
         for (; n_enq < P->prm.fixed_iters; ++n_enq) {
@@ -596,7 +596,7 @@ struct Runner {
       // A~(z0 + m dz) = exp(D m dz) psi_m (coupled operator: exp(i lam m dz) psi_m in the eigenbasis, which is
       // also the next large step's psi(z0) there)
       GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
-                                                   (const cplx<T>*)P->E + (size_t)m * nn, nn, P->stream));
+                                                   (const cplx<T>*)P->E + (size_t)m * nn, nn, P->ctrl, P->stream));
       s.large_steps++;
       s.small_steps += m;
       done += m;
