@@ -8,7 +8,7 @@ small steps per large step, dz = min(z_NL/200, z_IM/5) = 9.13 um.
 
 One benchmark step is one MPA large step (M small steps dz, iterated to the
 tolerance).  The metric is converged small steps dz per second.  Prints one
-JSON line.  Use --gpus 1 only: this build runs on one GPU.
+JSON line.  Use --gpus 1 only: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -286,7 +286,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the sub-step split of one large step is how it would shard).", file=sys.stderr)
         sys.exit(2)
 

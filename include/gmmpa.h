@@ -40,7 +40,7 @@ extern "C" {
 #define GMM_ERR_NOMEM (-2)       /* device allocation failed */
 #define GMM_ERR_TENSOR (-3)      /* coupling tensor lacks the symmetry the packed path needs */
 #define GMM_ERR_HIP (-4)         /* a HIP runtime call failed */
-#define GMM_ERR_UNSUPPORTED (-5) /* valid input outside what this build implements */
+#define GMM_ERR_UNSUPPORTED (-5) /* valid input outside what the library implements */
 #define GMM_ERR_DIVERGED (-6)    /* the iteration produced non-finite values */
 
 typedef struct gmm_plan_s* gmm_plan;

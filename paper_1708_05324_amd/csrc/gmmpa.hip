@@ -1121,9 +1121,9 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   const int Np = N * (N + 1) / 2;
   const int rpad = ((Np + 63) / 64) * 64;
   if (rpad > gmm::contract_max_rows())
-    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: the contraction exceeds 256 pair rows in this build");
+    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: the contraction exceeds 256 pair rows");
   if (bf16 && Np > gmm::kBf16Kpad)
-    return fail(GMM_ERR_UNSUPPORTED, "the BF16 split contraction supports up to 15 modes in this build");
+    return fail(GMM_ERR_UNSUPPORTED, "the BF16 split contraction supports up to 15 modes");
   // tensors: real [N^4] or complex [N^4][2] (s_complex); S^R = S^K when SR is NULL
   const size_t n4 = (size_t)N * N * N * N;
   const bool cplxS = p->s_complex == 1;
