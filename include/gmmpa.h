@@ -51,10 +51,10 @@ typedef enum {
   GMM_BF16X3 = 2  /* complex64 fields, FP32 transforms; contraction as S^hi B^hi + S^hi B^lo + S^lo B^hi
                      with bf16 hi/lo splits on MFMA, FP32 accumulation (up to 15 modes) */
 } gmm_precision;
-/* In GMM_FP32 and GMM_BF16X3 plans with Raman and Nt >= 2^13, the Raman
- * convolution drops the samples of h_R beyond the first Lh <= 1024 once their
- * absolute sum is at most 1e-9 of the whole (it then runs on 2^11-point
- * overlap-save segments); GMM_FP64 plans always convolve over the full window. */
+/* With Raman and Nt >= 2^13, the Raman convolution drops the samples of h_R
+ * beyond the first Lh <= 1024 once their absolute sum is at most 1e-9 (GMM_FP32,
+ * GMM_BF16X3) or 1e-17 (GMM_FP64) of the whole, and then runs on 2^11-point
+ * overlap-save segments; otherwise it convolves over the full window. */
 
 typedef struct {
   int n_modes;          /* N >= 1 spatial modes */

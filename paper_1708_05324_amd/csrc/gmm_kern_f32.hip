@@ -389,10 +389,10 @@ hipError_t launch_pairs_os(const cplx<float>* A, float* Bp, uint32_t* Bhi, uint3
   const int nseg = (Nt + V - 1) / V, total = nseg * ((Np + 1) / 2) * count;
   const dim3 grid(8 * ((total + 7) / 8));
   if (Bhi != nullptr)
-    hipLaunchKernelGGL((k_pairs_os<true>), grid, dim3(S::THREADS), 0, s, A, nullptr, Bhi, Blo, pairs, N, Np, count,
+    hipLaunchKernelGGL((k_pairs_os<float, true>), grid, dim3(S::THREADS), 0, s, A, nullptr, Bhi, Blo, pairs, N, Np, count,
                        kBf16Kpad / 8, Nt, Lh, V, nseg, Gf, twf, ctrl);
   else
-    hipLaunchKernelGGL((k_pairs_os<false>), grid, dim3(S::THREADS), 0, s, A, Bp, nullptr, nullptr, pairs, N, Np, count,
+    hipLaunchKernelGGL((k_pairs_os<float, false>), grid, dim3(S::THREADS), 0, s, A, Bp, nullptr, nullptr, pairs, N, Np, count,
                        kBf16Kpad / 8, Nt, Lh, V, nseg, Gf, twf, ctrl);
   return hipGetLastError();
 }

@@ -1158,7 +1158,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF1
 // pair, sub-step), XCD-local order with the segments of a row adjacent; two real
 // rows are one complex transform, as in k_conv; same outputs as k_conv.
 template <typename T, bool BF16OUT>
-__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), 5) void k_conv_os(
+__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), sizeof(T) == 4 ? 5 : 2) void k_conv_os(
     const T* __restrict__ Y, T* __restrict__ Yout, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo, int R,
     int RQ, int count, int KW, int Nt, int Lh, int V, int nseg, const cplx<T>* __restrict__ Gf,
     const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
@@ -1209,14 +1209,14 @@ __global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), 5)
 // from the fields, filters the segment and writes its valid outputs in the
 // layout of k_pairs (BF16OUT = false: rows [count][Np][Nt]) or of k_pairs_bf16
 // (hi/lo planes [count][KB][Nt][8]).
-template <bool BF16OUT>
-__global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS), 5) void k_pairs_os(
-    const cplx<float>* __restrict__ A, float* __restrict__ Bp, uint32_t* __restrict__ Bhi,
-    uint32_t* __restrict__ Blo, const int2* __restrict__ pairs, int N, int Np, int count, int KB, int Nt, int Lh,
-    int V, int nseg, const cplx<float>* __restrict__ Gf, const cplx<float>* __restrict__ twf, const Ctrl* ctrl) {
-  using S = FftShape<kOsLogF, 4, 4>;
+template <typename T, bool BF16OUT>
+__global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), sizeof(T) == 4 ? 5 : 2) void k_pairs_os(
+    const cplx<T>* __restrict__ A, T* __restrict__ Bp, uint32_t* __restrict__ Bhi, uint32_t* __restrict__ Blo,
+    const int2* __restrict__ pairs, int N, int Np, int count, int KB, int Nt, int Lh, int V, int nseg,
+    const cplx<T>* __restrict__ Gf, const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
+  using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
   if (skip_iteration(ctrl)) return;
-  __shared__ float lds[S::LDS_ELEMS];
+  __shared__ T lds[S::LDS_ELEMS];
   const int PB = (Np + 1) / 2;
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * PB * count);
   if (w < 0) return;
@@ -1227,28 +1227,28 @@ __global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS), 5) void k_pairs
   const int2 a = pairs[Q1];
   const int2 b = has2 ? pairs[Q2] : a;
   const bool share_m = b.x == a.x, share_n = b.y == a.y;
-  const cplx<float>* Aj = A + (size_t)jj * N * Nt;
-  const cplx<float>* am = Aj + (size_t)a.x * Nt;
-  const cplx<float>* an = Aj + (size_t)a.y * Nt;
-  const cplx<float>* bm = Aj + (size_t)b.x * Nt;
-  const cplx<float>* bn = Aj + (size_t)b.y * Nt;
+  const cplx<T>* Aj = A + (size_t)jj * N * Nt;
+  const cplx<T>* am = Aj + (size_t)a.x * Nt;
+  const cplx<T>* an = Aj + (size_t)a.y * Nt;
+  const cplx<T>* bm = Aj + (size_t)b.x * Nt;
+  const cplx<T>* bn = Aj + (size_t)b.y * Nt;
   const int t0 = seg * V, base = t0 - (Lh - 1);
-  cplx<float> z[S::R];
+  cplx<T> z[S::R];
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int t = (base + tid + i * S::THREADS) & (Nt - 1);
-    const cplx<float> x = am[t], y = an[t];
-    float b2 = 0.f;
+    const cplx<T> x = am[t], y = an[t];
+    T b2 = 0;
     if (has2) {
-      const cplx<float> u = share_m ? x : bm[t], v = share_n ? y : bn[t];
+      const cplx<T> u = share_m ? x : bm[t], v = share_n ? y : bn[t];
       b2 = u.re * v.re + u.im * v.im;
     }
     z[i] = {x.re * y.re + x.im * y.im, b2};
   }
-  block_fft<S, float, +1>(z, lds, tid, twf);
+  block_fft<S, T, +1>(z, lds, tid, twf);
 #pragma unroll
   for (int i = 0; i < S::R; ++i) z[i] = cmul(z[i], Gf[tid + i * S::THREADS]);
-  block_fft<S, float, -1>(z, lds, tid, twf);
+  block_fft<S, T, -1>(z, lds, tid, twf);
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int o = tid + i * S::THREADS - (Lh - 1);
@@ -1256,12 +1256,12 @@ __global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS), 5) void k_pairs
     if (o < 0 || o >= V || t >= Nt) continue;
     if constexpr (BF16OUT) {
       uint32_t h, l;
-      bf16_split2(z[i].re, has2 ? z[i].im : 0.f, h, l);
+      bf16_split2((float)z[i].re, has2 ? (float)z[i].im : 0.f, h, l);
       const size_t at = (((size_t)jj * KB + (Q1 >> 3)) * Nt) * 4 + ((Q1 & 7) >> 1) + (size_t)t * 4;
       Bhi[at] = h;
       Blo[at] = l;
     } else {
-      float* o1 = Bp + ((size_t)jj * Np + Q1) * Nt;
+      T* o1 = Bp + ((size_t)jj * Np + Q1) * Nt;
       o1[t] = z[i].re;
       if (has2) o1[Nt + t] = z[i].im;
     }

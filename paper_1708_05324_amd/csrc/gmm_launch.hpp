@@ -23,6 +23,12 @@ struct Launch {
   // back = false: dst = U (E .* src); back = true: dst = conj(E) .* (U^H src), per frequency (E may be null)
   static hipError_t mode_mix(bool back, const cplx<T>* src, long src_jrows, cplx<T>* dst, const cplx<T>* U,
                              const cplx<T>* E, int j0, int N, int nt, int count, const Ctrl* ctrl, hipStream_t s);
+  // Overlap-save Raman convolution in the field precision (rows out): rank-r rows Y -> Yout, and the packed
+  // route's pair rows from the fields A -> Bp [count][Np][Nt]; Gf / twf the 2^kOsLogF-point filter and twiddles
+  static hipError_t conv_os(const T* Y, T* Yout, int R, int RQ, int count, int Nt, int Lh, int V,
+                            const cplx<T>* Gf, const cplx<T>* twf, const Ctrl* ctrl, hipStream_t s);
+  static hipError_t pairs_os(const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np, int count, int Nt, int Lh,
+                             int V, const cplx<T>* Gf, const cplx<T>* twf, const Ctrl* ctrl, hipStream_t s);
   static hipError_t phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E, int N,
                                   int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,

@@ -90,6 +90,28 @@ hipError_t Launch<T>::mode_mix(bool back, const cplx<T>* src, long src_jrows, cp
 }
 
 template <typename T>
+hipError_t Launch<T>::conv_os(const T* Y, T* Yout, int R, int RQ, int count, int Nt, int Lh, int V,
+                              const cplx<T>* Gf, const cplx<T>* twf, const Ctrl* ctrl, hipStream_t s) {
+  using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
+  if (Lh < 1 || V < 1 || Lh - 1 + V > S::N || Nt < S::N || (Nt & (Nt - 1))) return hipErrorInvalidValue;
+  const int nseg = (Nt + V - 1) / V, total = nseg * ((R + 1) / 2) * count;
+  hipLaunchKernelGGL((k_conv_os<T, false>), dim3(8 * ((total + 7) / 8)), dim3(S::THREADS), 0, s, Y, Yout, nullptr,
+                     nullptr, R, RQ, count, 32, Nt, Lh, V, nseg, Gf, twf, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::pairs_os(const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np, int count, int Nt, int Lh,
+                               int V, const cplx<T>* Gf, const cplx<T>* twf, const Ctrl* ctrl, hipStream_t s) {
+  using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
+  if (Lh < 1 || V < 1 || Lh - 1 + V > S::N || Nt < S::N || (Nt & (Nt - 1))) return hipErrorInvalidValue;
+  const int nseg = (Nt + V - 1) / V, total = nseg * ((Np + 1) / 2) * count;
+  hipLaunchKernelGGL((k_pairs_os<T, false>), dim3(8 * ((total + 7) / 8)), dim3(S::THREADS), 0, s, A, Bp, nullptr,
+                     nullptr, pairs, N, Np, count, 0, Nt, Lh, V, nseg, Gf, twf, ctrl);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t Launch<T>::phase_to_time(int logn, const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* E,
                                     int N, int count, int j0, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {

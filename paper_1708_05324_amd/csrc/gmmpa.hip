@@ -160,10 +160,10 @@ struct gmm_plan_s {
   void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
   void* Vlo = nullptr;
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
-  // overlap-save form of the rank-r convolution (FP32 / BF16X3 plans, short Raman response)
+  // overlap-save form of the Raman convolution (short Raman response)
   int os_lh = 0, os_v = 0;  // kernel taps, outputs per 2^11-point segment (0: full-row transforms)
-  void* Gos = nullptr;      // [2^11] segment filter DFT_{+}(g) / 2^11, complex64
-  void* twos = nullptr;     // [2^11] exp(-2 pi i m / 2^11), complex64
+  void* Gos = nullptr;      // [2^11] segment filter DFT_{+}(g) / 2^11, field precision
+  void* twos = nullptr;     // [2^11] exp(-2 pi i m / 2^11), field precision
   // general-tensor route (S^R != S^K, complex S, or S without the packed symmetries)
   bool dense = false;
   int KD = 0, rows_pad = 0;  // real pair rows per sub-step (multiple of 4); output rows 2 N^2 padded to 64
@@ -390,16 +390,11 @@ struct Runner {
         }
       }
       if (!P->bf16) {
-        bool os_done = false;
-        if constexpr (std::is_same<T, float>::value) {
-          if (P->os_lh) {
-            if (doA)
-              GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, (float*)P->Bp, nullptr, nullptr, R, P->rq, count,
-                                                              P->nt, P->os_lh, P->os_v, (const cplx<float>*)P->Gos,
-                                                              (const cplx<float>*)P->twos, ctrl, P->stream));
-            os_done = true;
-          }
-        }
+        const bool os_done = P->os_lh != 0;
+        if (os_done && doA)
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv_os(Y, (T*)P->Bp, R, P->rq, count, P->nt, P->os_lh, P->os_v,
+                                                         (const cplx<T>*)P->Gos, (const cplx<T>*)P->twos, ctrl,
+                                                         P->stream));
         if (!os_done && doA)
           GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
                                                         (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
@@ -429,17 +424,11 @@ struct Runner {
       }
     }
     if (!P->bf16 && !P->factored && !P->dense) {
-      bool os_done = false;
-      if constexpr (std::is_same<T, float>::value) {
-        if (P->os_lh) {
-          if (doA)
-            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_os(W, (float*)P->Bp, nullptr, nullptr, P->pairs, P->N,
-                                                               P->Np, count, P->nt, P->os_lh, P->os_v,
-                                                               (const cplx<float>*)P->Gos,
-                                                               (const cplx<float>*)P->twos, ctrl, P->stream));
-          os_done = true;
-        }
-      }
+      const bool os_done = P->os_lh != 0;
+      if (os_done && doA)
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_os(W, (T*)P->Bp, P->pairs, P->N, P->Np, count, P->nt, P->os_lh,
+                                                        P->os_v, (const cplx<T>*)P->Gos, (const cplx<T>*)P->twos, ctrl,
+                                                        P->stream));
       if (doA && !os_done)
         GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
@@ -1036,17 +1025,18 @@ int build_raman(gmm_plan_s* P, const double* hR, double blend) {
   return GMM_OK;
 }
 
-// Overlap-save filter of every route with Raman (FP32 / BF16X3 plans; the general route filters with
-// h_R alone, blend = 1): the normalised
-// weights w_k of h_R are cut after the first Lh samples once the absolute sum of
-// everything beyond (the causal tail and the wrapped samples near Nt) is at most
-// kOsTail of their absolute sum, far below the field precision.  Segments of
-// F = 2^11 points then give V = F - Lh + 1 outputs each.  Used for Nt >= 2^13
-// and Lh <= F / 2 (at least half of each segment is output); otherwise the plan
-// keeps the full-row transforms.
-constexpr double kOsTail = 1e-9;
-
+// Overlap-save filter of every route with Raman (the general route filters
+// with h_R alone, blend = 1): the normalised weights w_k of h_R are cut after
+// the first Lh samples once the absolute sum of everything beyond (the causal
+// tail and the wrapped samples near Nt) is at most the precision's tail bound
+// of their absolute sum.  Segments of F = 2^11 points then give V = F - Lh + 1
+// outputs each.  Used for Nt >= 2^13 and Lh <= F / 2 (at least half of each
+// segment is output); otherwise the plan keeps the full-row transforms.
+template <typename T>
 int build_overlap_save(gmm_plan_s* P, const double* hR, double blend) {
+  // tail bound: far below the rounding of the field precision (FP64: below its unit roundoff, so the segmented
+  // convolution equals the full-window one to rounding)
+  const double tail_bound = sizeof(T) == 4 ? 1e-9 : 1e-17;
   constexpr int F = 1 << gmm::kOsLogF;
   const int n = P->nt;
   if (n < 8192) return GMM_OK;
@@ -1055,24 +1045,24 @@ int build_overlap_save(gmm_plan_s* P, const double* hR, double blend) {
   for (int k = 0; k < n; ++k) asum += std::fabs(hR[k] / sum);
   int lh = n;
   double tail = 0.0;
-  while (lh > 1 && tail + std::fabs(hR[lh - 1] / sum) <= kOsTail * asum) tail += std::fabs(hR[--lh] / sum);
+  while (lh > 1 && tail + std::fabs(hR[lh - 1] / sum) <= tail_bound * asum) tail += std::fabs(hR[--lh] / sum);
   if (lh > F / 2) return GMM_OK;
   std::vector<std::complex<double>> g(F, 0.0);
   for (int k = 0; k < lh; ++k) g[k] = blend * hR[k] / sum;
   g[0] += 1.0 - blend;
   host_fft_plus(g);
-  std::vector<cplx<float>> gf(F), tf(F);
+  std::vector<cplx<T>> gf(F), tf(F);
   for (int k = 0; k < F; ++k) {
-    gf[k] = cplx<float>{(float)(g[k].real() / F), (float)(g[k].imag() / F)};
+    gf[k] = cplx<T>{(T)(g[k].real() / F), (T)(g[k].imag() / F)};
     const std::complex<double> t = std::polar(1.0, -2.0 * kPi * (double)k / F);
-    tf[k] = cplx<float>{(float)t.real(), (float)t.imag()};
+    tf[k] = cplx<T>{(T)t.real(), (T)t.imag()};
   }
   int rc;
-  if ((rc = dev_alloc(&P->const_bytes, &P->Gos, F * sizeof(cplx<float>))) ||
-      (rc = dev_alloc(&P->const_bytes, &P->twos, F * sizeof(cplx<float>))))
+  if ((rc = dev_alloc(&P->const_bytes, &P->Gos, F * sizeof(cplx<T>))) ||
+      (rc = dev_alloc(&P->const_bytes, &P->twos, F * sizeof(cplx<T>))))
     return rc;
-  GMM_HIP(hipMemcpy(P->Gos, gf.data(), F * sizeof(cplx<float>), hipMemcpyHostToDevice));
-  GMM_HIP(hipMemcpy(P->twos, tf.data(), F * sizeof(cplx<float>), hipMemcpyHostToDevice));
+  GMM_HIP(hipMemcpy(P->Gos, gf.data(), F * sizeof(cplx<T>), hipMemcpyHostToDevice));
+  GMM_HIP(hipMemcpy(P->twos, tf.data(), F * sizeof(cplx<T>), hipMemcpyHostToDevice));
   P->os_lh = lh;
   P->os_v = F - lh + 1;
   return GMM_OK;
@@ -1248,7 +1238,9 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
       rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
     }
-    if (!fp64 && (rc = build_overlap_save(P, hR, blend))) return bail(rc);
+    if (!(fp64 && dense) &&  // the general route's segmented rows exist for complex64 fields only
+        (rc = fp64 ? build_overlap_save<double>(P, hR, blend) : build_overlap_save<float>(P, hR, blend)))
+      return bail(rc);
   }
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
   if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||

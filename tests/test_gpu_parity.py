@@ -633,7 +633,7 @@ def test_general_route_21_modes_with_gain(torch_gpu, prec):
     assert err < TOL_OP[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("dt", [5e-15, 0.5e-15], ids=["short_response_overlap_save", "long_response_full_rows"])
 @pytest.mark.parametrize("groups", [5, 3], ids=["rank45_route", "packed_route"])
 def test_raman_convolution_forms_2_to_13(torch_gpu, prec, dt, groups):
