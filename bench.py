@@ -95,7 +95,13 @@ def read_traffic(kind: str, workload: str, prec: str):
     return float(m_b.group(1))
 
 
-def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool, make_plan=None):
+def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool, make_plan=None,
+            repeats: int = 5):
+    """Time `repeats` windows of `steps` large steps each (no per-kernel events
+    inside them) and report the median window.  With `profile`, the warm-up
+    times every kernel kind (per-kernel breakdown), and one more window of
+    `steps` large steps after the timed ones brackets each launch of the
+    dominant kind with HIP events on the plan's stream (roofline)."""
     import torch
     from paper_1708_05324_amd import gmmpa
     plan = (make_plan(prec) if make_plan else
@@ -115,34 +121,55 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
         if profile:
             breakdown = {k: (v[0] / wres.stats["large_steps"], v[1]) for k, v in plan.profile_read().items()}
             dominant = max(breakdown, key=lambda k: breakdown[k][0])
-    # timed region: events only around the dominant kernel kind (two per launch)
-    plan.profile([dominant] if dominant else False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = plan.propagate(A, steps * Ls, w.dz, w.M)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = {dominant: plan.profile_read()[dominant]} if dominant else None
-    plan.profile(False)
+        plan.profile(False)
+    windows = []
+    for _ in range(max(1, repeats)):  # timed windows: only propagate between the two synchronisations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.propagate(A, steps * Ls, w.dz, w.M)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        A = res.field
+        st = res.stats
+        windows.append({"seconds": t1 - t0, "stats": st})
+    order = sorted(range(len(windows)), key=lambda i: windows[i]["seconds"])
+    med = windows[order[len(order) // 2]]
+    prof, prof_window = None, None
+    if dominant:                      # roofline window: events around each launch of the dominant kind
+        plan.profile([dominant])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pres = plan.propagate(A, steps * Ls, w.dz, w.M)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = {dominant: plan.profile_read()[dominant]}
+        prof_window = {"seconds": t1 - t0, "stats": pres.stats}
+        plan.profile(False)
+        A = pres.field
     lat = []
     solve_L = 11 * Ls                      # one "solve": 110 small steps (about 1 mm)
-    B = res.field
+    B = A
     for _ in range(latency_solves):
         torch.cuda.synchronize()
         a = time.perf_counter()
         B = plan.propagate(B, solve_L, w.dz, w.M).field
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
-    st = res.stats
+    st = med["stats"]
+    sec = med["seconds"]
     out = {
-        "seconds": t1 - t0,
-        "small_steps_per_s": st["small_steps"] / (t1 - t0),
-        "ms_per_large_step": (t1 - t0) / st["large_steps"] * 1e3,
+        "seconds": sec,
+        "small_steps_per_s": st["small_steps"] / sec,
+        "ms_per_large_step": sec / st["large_steps"] * 1e3,
         "iterations_per_large_step": st["iterations"] / st["large_steps"],
-        "evaluations_per_s": st["evaluations"] / (t1 - t0),
+        "evaluations_per_s": st["evaluations"] / sec,
         "nonconverged_steps": st["nonconverged_steps"],
+        "windows_small_steps_per_s": [round(x["stats"]["small_steps"] / x["seconds"], 1) for x in windows],
         "stats": st,
         "prof": prof,
+        "prof_stats": prof_window["stats"] if prof_window else None,
+        "prof_window_small_steps_per_s": (prof_window["stats"]["small_steps"] / prof_window["seconds"]
+                                          if prof_window else None),
         "breakdown": breakdown,
         "rank": rank,
     }
@@ -151,8 +178,36 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
         out["latency_ms_p50"] = lat[len(lat) // 2]
         out["latency_ms_p99"] = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
         out["latency_small_steps"] = int(round(solve_L / w.dz))
+        out["latency_solves"] = len(lat)
     plan.close()
     return out
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "metric_22_large_steps.npz")
+
+
+def field_error_vs_oracle(prec: str, w, make_plan=None):
+    """Max field error, normalised by the peak, after the oracle golden's
+    propagation (22 large steps of the metric workload, about 2 mm) run in the
+    benchmark's own mode (tolerance per precision), against the FP64 oracle's
+    stored result (tests/golden, written by a script that calls only the oracle)."""
+    import numpy as np
+    import torch
+    from paper_1708_05324_amd import gmmpa
+    if not os.path.exists(GOLDEN):
+        return None
+    g = np.load(GOLDEN)
+    plan = (make_plan(prec) if make_plan else
+            gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30))
+    dtype = torch.complex128 if prec == "fp64" else torch.complex64
+    A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
+    res = plan.propagate(A, float(g["L"]), float(g["dz"]), int(g["M"]))
+    got = res.field.cpu().numpy()
+    plan.close()
+    ref = g["A_ref"]
+    return {"field_error": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+            "length_small_steps": int(res.stats["small_steps"]), "reference": "FP64 oracle, tol 1e-12",
+            "iterations": int(res.stats["iterations"])}
 
 
 def run_rk4ip(prec: str, w, n_steps: int) -> float:
@@ -233,16 +288,20 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
 
 def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
     """The FP64 oracle on the host: large steps (M small steps each) of the same
-    workload from its launch field, until at least min_seconds of work."""
+    workload from its launch field, until at least min_seconds of work.  The
+    oracle's transforms are numpy.fft (one thread); its matrix products use the
+    BLAS thread pool.  `cores` is the average number of busy threads over the
+    sample (process CPU time / wall time), the pool size is stated beside it."""
     from oracle import gmmnlse as O
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        pool = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        pool = os.cpu_count() or 1
     m = O.model_from_workload(w)
     A = w.A0
     n_large, iters, evals = 0, 0, 0
+    c0 = time.process_time()
     t0 = time.perf_counter()
     while n_large < max_large_steps and (n_large == 0 or time.perf_counter() - t0 < min_seconds):
         A, st = O.mpa_propagate(A, m, w.M * w.dz, w.dz, w.M, tol=TOL["fp64"], max_iter=30, return_stats=True)
@@ -250,10 +309,13 @@ def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
         iters += sum(st.iterations)
         evals += st.evaluations
     sec = time.perf_counter() - t0
-    return {"value": round(n_large * w.M / sec, 4), "unit": "small steps/s", "cores": int(threads), "kind": "oracle",
+    busy = (time.process_time() - c0) / sec
+    return {"value": round(n_large * w.M / sec, 4), "unit": "small steps/s", "cores": max(1, int(round(busy))),
+            "kind": "oracle",
             "sample": f"{n_large} large steps ({n_large * w.M} small steps of {w.dz * 1e6:.2f} um) of the same "
                       f"workload from its launch field, FP64, tol 1e-12 ({iters} iterations, {evals} evaluations) "
-                      f"in {sec:.1f} s"}
+                      f"in {sec:.1f} s; {busy:.1f} threads busy on average (numpy.fft single-threaded, BLAS "
+                      f"pool of {pool} threads for the products), {os.cpu_count()} host CPUs"}
 
 
 def main():
@@ -264,7 +326,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison runs in the other precisions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--latency-solves", type=int, default=20)
+    ap.add_argument("--latency-solves", type=int, default=100)
+    ap.add_argument("--repeats", type=int, default=5, help="timed windows of --steps large steps (median reported)")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--sweep-M", action="store_true",
                     help="only run the parallel-extent sweep M = 1..40 (M = 1 is the serial trapezoid) and the "
@@ -409,17 +472,30 @@ def main():
     N, Nt = w.n_modes, w.nt
     workload = "grin15_raman_nt16384"
 
-    main_run = run_gpu(args.precision, w, args.steps, args.warmup, args.latency_solves, not args.no_profile)
+    main_run = run_gpu(args.precision, w, args.steps, args.warmup, args.latency_solves, not args.no_profile,
+                       repeats=args.repeats)
+    main_acc = field_error_vs_oracle(args.precision, w)
     extra = {}
     if not args.no_compare:
         for other in ("bf16x3", "fp32", "fp64"):
             if other == args.precision:
                 continue
-            o = run_gpu(other, w, max(8, args.steps // 2), 1, 0, False)
+            o = run_gpu(other, w, args.steps, 1, 0, False, repeats=args.repeats)
             extra[other] = {"small_steps_per_s": round(o["small_steps_per_s"], 2),
                             "evaluations_per_s": round(o["evaluations_per_s"], 2),
                             "iterations_per_large_step": round(o["iterations_per_large_step"], 3),
-                            "ms_per_large_step": round(o["ms_per_large_step"], 4), "tol": TOL[other]}
+                            "ms_per_large_step": round(o["ms_per_large_step"], 4), "tol": TOL[other],
+                            "accuracy_2mm": field_error_vs_oracle(other, w)}
+        # the packed contraction route (the full-rank form an Eq. (2) tensor of a mode solver would take)
+        o = run_gpu(args.precision, w, args.steps, 1, 0, False, repeats=args.repeats,
+                    make_plan=lambda p: gmmpa.plan_from_workload(w, precision=p, tol=TOL[p], max_iter=30,
+                                                                 factor_policy=1))
+        extra[f"{args.precision}_packed_route"] = {
+            "small_steps_per_s": round(o["small_steps_per_s"], 2),
+            "evaluations_per_s": round(o["evaluations_per_s"], 2),
+            "iterations_per_large_step": round(o["iterations_per_large_step"], 3),
+            "ms_per_large_step": round(o["ms_per_large_step"], 4), "tol": TOL[args.precision],
+            "route": "packed matrix S^ (120 x 120), no rank factor"}
     line = {
         "metric": "MPA steps/s at N=15 modes, Nt=2^14 (BF16/FP32 vs FP64); p50/p99 solve latency",
         "value": round(main_run["small_steps_per_s"], 2),
@@ -439,14 +515,19 @@ def main():
                    "parallelism": "single GPU"},
         "iterations_per_large_step": round(main_run["iterations_per_large_step"], 3),
         "evaluations_per_s": round(main_run["evaluations_per_s"], 2),
+        "timed_windows_small_steps_per_s": main_run["windows_small_steps_per_s"],
+        "accuracy_2mm": main_acc,
         "latency_ms_p50": round(main_run.get("latency_ms_p50", float("nan")), 3),
         "latency_ms_p99": round(main_run.get("latency_ms_p99", float("nan")), 3),
-        "latency_solve": f"{main_run.get('latency_small_steps')} small steps per solve",
+        "latency_solve": (f"{main_run.get('latency_solves')} back-to-back solves of "
+                          f"{main_run.get('latency_small_steps')} small steps on one warm plan (solve latency, "
+                          f"not a served latency)"),
         "compare": extra,
     }
     if main_run["prof"]:
-        line["roofline"] = roofline(main_run["prof"], main_run["stats"], N, Nt, args.precision, workload,
+        line["roofline"] = roofline(main_run["prof"], main_run["prof_stats"], N, Nt, args.precision, workload,
                                     main_run["rank"])
+        line["roofline"]["window_small_steps_per_s"] = round(main_run["prof_window_small_steps_per_s"], 1)
     if main_run["breakdown"]:
         line["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in main_run["breakdown"].items()}
     if not args.no_cpu_baseline:

@@ -42,8 +42,10 @@ extern "C" {
 #define GMM_ERR_HIP (-4)         /* a HIP runtime call failed */
 #define GMM_ERR_UNSUPPORTED (-5) /* valid input outside what the library implements */
 #define GMM_ERR_DIVERGED (-6)    /* the iteration produced non-finite values */
+#define GMM_ERR_BUSY (-7)        /* a batch has no free slot */
 
 typedef struct gmm_plan_s* gmm_plan;
+typedef struct gmm_batch_s* gmm_batch;
 
 typedef enum {
   GMM_FP64 = 0,   /* complex128 fields, FP64 transforms, FP64 MFMA contraction */
@@ -203,6 +205,50 @@ int gmm_plan_set_coupling_exact(gmm_plan plan, const double* Q, int q_complex);
  * Queued on the plan's stream; returns without synchronising.
  */
 int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out);
+
+/*
+ * Batched propagations of one plan with continuous admission: the MPA of
+ * Sec. III.D for up to `slots` independent propagations at once, each with its
+ * own launch field, length and step (same plan: modes, tensors, grid,
+ * precision, M).  Work advances in rounds: a round is one MPA iteration of
+ * every running propagation, queued as one launch per kernel kind over the
+ * sub-step rows of all of them; then the trapezoid rule and the FP64
+ * convergence norm per propagation, and one read-back of all stop flags.  A
+ * propagation whose large step converged closes it and starts the next in the
+ * following round; one that reached its length is transformed back, reported
+ * and its slot freed, and gmm_batch_submit can admit a new one there while the
+ * others run.  Per propagation the result, statistics and iteration counts are
+ * bit for bit those of gmm_propagate on the same plan.  The plan must outlive
+ * the batch and have the gain and coupling terms off (GMM_ERR_UNSUPPORTED).
+ *
+ * gmm_batch_create  - allocate the device buffers of `slots` propagations with
+ *                     M small steps per large step (all queued on the plan's
+ *                     stream).
+ * gmm_batch_submit  - admit one propagation into a free slot: A0 device [N][Nt]
+ *                     (read before the call's queued work ends: keep it alive
+ *                     until the next gmm_batch_wait), length L, requested step
+ *                     dz (same rule as gmm_propagate), Aout device [N][Nt]
+ *                     written when it completes, `tag` returned with it.
+ *                     Returns the slot index (>= 0), or GMM_ERR_BUSY when every
+ *                     slot is taken.  Allowed while a round is queued.
+ * gmm_batch_launch  - queue one round (no host wait).  GMM_ERR_ARG if a round
+ *                     is queued and not yet waited for.
+ * gmm_batch_wait    - wait for the queued round (nothing to do if none) and
+ *                     report the propagations that completed in it: their tags,
+ *                     return codes (GMM_OK, GMM_NOT_CONVERGED, GMM_ERR_DIVERGED)
+ *                     and statistics into tags / status / stats (status and stats
+ *                     may be NULL; arrays of max_done >= slots entries);
+ *                     *n_done is their count.  Returns the number of
+ *                     propagations still in the batch (0: idle), or an error.
+ * gmm_batch_destroy - release the batch (waits for a queued round).
+ * gmm_batch_device_bytes - device bytes the batch holds.
+ */
+int gmm_batch_create(gmm_batch* out, gmm_plan plan, int slots, int M);
+int gmm_batch_submit(gmm_batch b, const void* A0, double L, double dz, void* Aout, long long tag);
+int gmm_batch_launch(gmm_batch b);
+int gmm_batch_wait(gmm_batch b, long long* tags, int* status, gmm_stats* stats, int max_done, int* n_done);
+int gmm_batch_destroy(gmm_batch b);
+long long gmm_batch_device_bytes(gmm_batch b);
 
 /* Release every device buffer of the plan.  NULL is accepted. */
 int gmm_plan_destroy(gmm_plan plan);

@@ -16,6 +16,29 @@ struct Ctrl {
 };
 
 
+// Batched rounds (see the batched kernels): one row of a round, and the per-slot part.
+struct BatchRow {
+  int slot;  // slot index
+  int src;   // source iterate: -1 = the slot's psi_0, else its sub-step row (j - 1)
+  int ej;    // sub-step j of the phase factor exp(D_w j dz) (row of the slot's table)
+  int pad;
+};
+
+// Per-slot part of a batched iteration (trapezoid, norm) or large-step close.
+struct BatchSlot {
+  const void* psi0;   // [N][Nt] psi(z0)
+  const void* I0;     // I_0: the round's row of sub-step 0 (first iteration) or the slot's kept copy
+  const void* I;      // the round's first row of sub-step 1
+  void* psi;          // [M][N][Nt] sub-step iterates (close: its row m - 1 is the source)
+  void* I0_keep;      // [N][Nt] kept I_0
+  void* dst;          // close: psi(z0 + m dz) goes here (the slot's psi_0)
+  const void* Em;     // close: exp(D_w m dz) row of the slot's table
+  double* partials;   // [trapz_blocks(N Nt)][2] FP64 partial sums of the norm
+  Ctrl* ctrl;         // the slot's control block
+  double dz;
+  int first, m;
+};
+
 // Most modes the saturating-gain kernels take (their N x N matrices sit in LDS),
 // and the samples per partial sum of the pair integrals.
 constexpr int kGainNmax = 22;

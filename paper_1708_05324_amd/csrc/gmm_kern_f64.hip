@@ -6,9 +6,8 @@ template struct gmm::Launch<double>;
 namespace gmm {
 
 // Fixed-order reduction of the partial sums and the stopping decision.
-__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
-                                                     double tol, int fixed_iters, int max_iter) {
-  if (skip_iteration(ctrl)) return;
+__device__ __forceinline__ void norm_final_block(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
+                                                 double tol, int fixed_iters, int max_iter) {
   __shared__ double red[2][256];
   double d = 0.0, s = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 256) {
@@ -26,7 +25,9 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double eps = red[1][0] > 0.0 ? sqrt(red[0][0] / red[1][0]) : 0.0;
+    const double dn = red[0][0], sn = red[1][0];
+    // a non-finite sum means a non-finite field value: report it (eps = NaN), never as converged
+    const double eps = (!isfinite(dn) || !isfinite(sn)) ? __builtin_nan("") : sn > 0.0 ? sqrt(dn / sn) : 0.0;
     const int it = ctrl->iters + 1;
     ctrl->eps = eps;
     ctrl->iters = it;
@@ -42,6 +43,19 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
       ctrl->done = 1;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
+                                                     double tol, int fixed_iters, int max_iter) {
+  if (skip_iteration(ctrl)) return;
+  norm_final_block(partials, nblocks, ctrl, tol, fixed_iters, max_iter);
+}
+
+// One block per slot of a batched round.
+__global__ __launch_bounds__(256) void k_norm_final_b(const BatchSlot* __restrict__ slots, int nblocks, double tol,
+                                                       int fixed_iters, int max_iter) {
+  const BatchSlot d = slots[blockIdx.x];
+  norm_final_block(d.partials, nblocks, d.ctrl, tol, fixed_iters, max_iter);
 }
 
 __global__ void k_ctrl_reset(Ctrl* ctrl) {
@@ -123,6 +137,13 @@ hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double
   hipLaunchKernelGGL(k_gain_matrix, dim3(N, count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, K, Mg, N, ctrl);
   return hipGetLastError();
 }
+hipError_t launch_norm_final_b(const BatchSlot* slots, int nslots, int nblocks, double tol, int fixed_iters,
+                               int max_iter, hipStream_t s) {
+  if (nslots < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_norm_final_b, dim3(nslots), dim3(256), 0, s, slots, nblocks, tol, fixed_iters, max_iter);
+  return hipGetLastError();
+}
+
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, ctrl);
   return hipGetLastError();

@@ -202,17 +202,11 @@ __global__ __launch_bounds__(256) void k_mode_mix(const cplx<T>* src, long src_j
 // grid (N, count); psi row (jj, p) at psi + (jj * psi_jrows + p) * Nt, where
 // psi_jrows is a row count: N for one field per sub-step, 0 to reuse psi_0.
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
-    const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* __restrict__ E, int j0,
-    const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+__device__ __forceinline__ void phase_to_time_row(const cplx<T>* src, const cplx<T>* __restrict__ ph,
+                                                  cplx<T>* dst, T* lds, int tid, const cplx<T>* __restrict__ tw) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
-  if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
-  const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
-  const cplx<T>* src = psi + ((size_t)jj * psi_jrows + p) * S::N;
   cplx<T> v[S::R];
-  if (E != nullptr) {
-    const cplx<T>* ph = E + ((size_t)(j0 + jj) * N + p) * S::N;
+  if (ph != nullptr) {
 #pragma unroll
     for (int i = 0; i < S::R; ++i) {
       const int k = tid + i * S::THREADS;
@@ -223,9 +217,21 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
     for (int i = 0; i < S::R; ++i) v[i] = src[tid + i * S::THREADS];
   }
   block_fft<S, T, -1>(v, lds, tid, tw);
-  cplx<T>* dst = A + ((size_t)jj * N + p) * S::N;
 #pragma unroll
   for (int i = 0; i < S::R; ++i) dst[tid + i * S::THREADS] = v[i];
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
+    const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* __restrict__ E, int j0,
+    const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T)>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
+  const cplx<T>* src = psi + ((size_t)jj * psi_jrows + p) * S::N;
+  const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
+  phase_to_time_row<T, LOGN>(src, ph, A + ((size_t)jj * N + p) * S::N, lds, threadIdx.x, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1397,19 +1403,14 @@ constexpr int kSpectralLogR = LOGN <= 14 ? 4 : 5;
 // F{.} = (1/Nt) FFT_{+}; gscale = gamma^ / Nt; exp(-D_w z_j) = conj(E[j0 + jj])
 // (E = nullptr: z = 0).  grid (N, count); in may alias out.
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out(
-    const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ E, int j0, double domega, double gscale,
-    double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+__device__ __forceinline__ void spectral_out_row(const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ ph,
+                                                 double domega, double gscale, double inv_omega0, int shock, T* lds,
+                                                 int tid, const cplx<T>* __restrict__ tw) {
   using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
-  if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
-  const int tid = threadIdx.x, p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
-  const size_t row = ((size_t)jj * N + p) * S::N;
   cplx<T> v[S::R];
 #pragma unroll
-  for (int i = 0; i < S::R; ++i) v[i] = in[row + tid + i * S::THREADS];
+  for (int i = 0; i < S::R; ++i) v[i] = in[tid + i * S::THREADS];
   block_fft<S, T, +1>(v, lds, tid, tw);
-  const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
 #pragma unroll
   for (int i = 0; i < S::R; ++i) {
     const int k = tid + i * S::THREADS;
@@ -1419,8 +1420,21 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>
       const cplx<T> e = ph[k];
       x = cmul(x, cplx<T>{e.re, -e.im});
     }
-    out[row + k] = cplx<T>{-f * x.im, f * x.re};
+    out[k] = cplx<T>{-f * x.im, f * x.re};
   }
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out(
+    const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ E, int j0, double domega, double gscale,
+    double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+  if (skip_iteration(ctrl)) return;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
+  const size_t row = ((size_t)jj * N + p) * S::N;
+  const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
+  spectral_out_row<T, LOGN>(in + row, out + row, ph, domega, gscale, inv_omega0, shock, lds, threadIdx.x, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1430,11 +1444,10 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>
 // and I_0 arrives in I0 as part of the first iteration's batch; it is copied to
 // I0_keep for the later iterations of the large step.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trapz(
-    const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
-    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, int first, int M, long nn, T dz,
-    double* __restrict__ partials, const Ctrl* ctrl) {
-  if (skip_iteration(ctrl)) return;
+__device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0,
+                                            const cplx<T>* __restrict__ I, cplx<T>* __restrict__ psi,
+                                            cplx<T>* __restrict__ I0_keep, int first, int M, long nn, T dz,
+                                            double* __restrict__ partials) {
   __shared__ double red[2][256];
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
@@ -1472,6 +1485,15 @@ __global__ __launch_bounds__(256) void k_trapz(
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_trapz(
+    const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
+    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, int first, int M, long nn, T dz,
+    double* __restrict__ partials, const Ctrl* ctrl) {
+  if (skip_iteration(ctrl)) return;
+  trapz_block<T>(psi0, I0, I, psi, I0_keep, first, M, nn, dz, partials);
+}
+
 // a9: psi0 <- exp(D_w z_m) * src (element-wise over [N][Nt]); Em = E[m].
 template <typename T>
 __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
@@ -1486,6 +1508,72 @@ __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, 
   }
   if (e >= nn) return;
   dst[e] = cmul(src[e], Em[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Batched iterations: several propagations ("slots") of one plan advance
+// together, each with its own step size, length and convergence.  Per-slot
+// buffers sit at fixed strides: psi_0 and I_0 [S][N][Nt], the sub-step
+// iterates [S][M][N][Nt], the phase tables [S][M + 1][N][Nt].  One launch
+// evaluates the sub-step rows of every slot that iterates in the round, listed
+// in a row table; the field rows of the round are packed into `work`.  The
+// kernels below do per row (per slot) exactly what their single-propagation
+// counterparts do, through the same device functions, so a slot's result is
+// bit for bit that of the same propagation run alone.
+// (BatchRow and BatchSlot are defined in gmm_common.hpp.)
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time_b(
+    const BatchRow* __restrict__ rows, const cplx<T>* psi0, const cplx<T>* psi, const cplx<T>* __restrict__ E,
+    cplx<T>* A, int M, const cplx<T>* __restrict__ tw) {
+  using S = FftShape<LOGN, (int)sizeof(T)>;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
+  const BatchRow d = rows[r];
+  const size_t nn = (size_t)N * S::N;
+  const cplx<T>* src = (d.src < 0 ? psi0 + (size_t)d.slot * nn : psi + ((size_t)d.slot * M + d.src) * nn) +
+                       (size_t)p * S::N;
+  const cplx<T>* ph = E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
+  phase_to_time_row<T, LOGN>(src, ph, A + ((size_t)r * N + p) * S::N, lds, threadIdx.x, tw);
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out_b(
+    const BatchRow* __restrict__ rows, cplx<T>* W, const cplx<T>* __restrict__ E, int M, double domega,
+    double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw) {
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+  __shared__ T lds[S::LDS_ELEMS];
+  const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
+  const BatchRow d = rows[r];
+  const size_t nn = (size_t)N * S::N;
+  cplx<T>* row = W + ((size_t)r * N + p) * S::N;
+  const cplx<T>* ph = E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
+  spectral_out_row<T, LOGN>(row, row, ph, domega, gscale, inv_omega0, shock, lds, threadIdx.x, tw);
+}
+
+// grid (trapz_blocks(nn), slots of the round)
+template <typename T>
+__global__ __launch_bounds__(256) void k_trapz_b(const BatchSlot* __restrict__ slots, long nn) {
+  const BatchSlot d = slots[blockIdx.y];
+  trapz_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
+                 (cplx<T>*)d.I0_keep, d.first, d.m, nn, (T)d.dz, d.partials);
+}
+
+// grid (trapz_blocks(nn), slots closing): psi_0 <- Em .* psi_{m}, and a fresh control block
+template <typename T>
+__global__ __launch_bounds__(256) void k_close_b(const BatchSlot* __restrict__ slots, long nn) {
+  const BatchSlot d = slots[blockIdx.y];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) {
+    d.ctrl->eps = 0.0;
+    d.ctrl->iters = 0;
+    d.ctrl->done = 0;
+    d.ctrl->status = 0;
+    d.ctrl->pad = 0;
+  }
+  if (e >= nn) return;
+  const cplx<T>* src = (const cplx<T>*)d.psi + (size_t)(d.m - 1) * nn;
+  ((cplx<T>*)d.dst)[e] = cmul(src[e], ((const cplx<T>*)d.Em)[e]);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,8 @@ namespace gmm {
 template <typename T>
 struct cplx;
 struct Ctrl;
+struct BatchRow;
+struct BatchSlot;
 
 template <typename T>
 struct Launch {
@@ -66,6 +68,16 @@ struct Launch {
   static hipError_t spec_sums(const cplx<T>* At, int nt, long nn, double domega, double omega0, double* partials,
                               hipStream_t s);
   static hipError_t finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, double fR, hipStream_t s);
+  // Batched rounds (several propagations of one plan): R rows listed in `rows`, per-slot buffers at fixed
+  // strides (psi0 [S][N][Nt], psi [S][M][N][Nt], E [S][M + 1][N][Nt]); work rows [R][N][Nt].
+  static hipError_t phase_to_time_b(int logn, const BatchRow* rows, const cplx<T>* psi0, const cplx<T>* psi,
+                                    const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw,
+                                    hipStream_t s);
+  static hipError_t spectral_out_b(int logn, const BatchRow* rows, cplx<T>* W, const cplx<T>* E, int N, int R, int M,
+                                   double domega, double gscale, double inv_omega0, int shock, const cplx<T>* tw,
+                                   hipStream_t s);
+  static hipError_t trapz_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s);
+  static hipError_t close_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s);
 };
 
 // BF16 split contraction path (complex64 fields, Np <= 128).
@@ -111,6 +123,9 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+// Norm reduction and stop decision for each slot of a batched round (one block per slot).
+hipError_t launch_norm_final_b(const BatchSlot* slots, int nslots, int nblocks, double tol, int fixed_iters,
+                               int max_iter, hipStream_t s);
 // Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn) (g may be NULL) + K_pl (K may be NULL),
 // Phi = dt * sum of the chunk partials.
 hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double>* SR, const double* g,

@@ -340,4 +340,44 @@ hipError_t Launch<T>::finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, doubl
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t Launch<T>::phase_to_time_b(int logn, const BatchRow* rows, const cplx<T>* psi0, const cplx<T>* psi,
+                                      const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw,
+                                      hipStream_t s) {
+  if (R < 1) return hipSuccess;
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, (int)sizeof(T)>;
+    hipLaunchKernelGGL((k_phase_to_time_b<T, LOGN>), dim3(N, R), dim3(S::THREADS), 0, s, rows, psi0, psi, E, A, M,
+                       tw);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::spectral_out_b(int logn, const BatchRow* rows, cplx<T>* W, const cplx<T>* E, int N, int R,
+                                     int M, double domega, double gscale, double inv_omega0, int shock,
+                                     const cplx<T>* tw, hipStream_t s) {
+  if (R < 1) return hipSuccess;
+  GMM_LOGN_SWITCH(logn, {
+    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+    hipLaunchKernelGGL((k_spectral_out_b<T, LOGN>), dim3(N, R), dim3(S::THREADS), 0, s, rows, W, E, M, domega, gscale,
+                       inv_omega0, shock, tw);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::trapz_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s) {
+  if (nslots < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_trapz_b<T>), dim3(trapz_blocks(nn), nslots), dim3(256), 0, s, slots, nn);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::close_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s) {
+  if (nslots < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_close_b<T>), dim3(trapz_blocks(nn), nslots), dim3(256), 0, s, slots, nn);
+  return hipGetLastError();
+}
+
 }  // namespace gmm

@@ -129,6 +129,11 @@ struct GmmProfiler {
   void reset() {
     for (int k = 0; k < GMM_PROF_KINDS; ++k) ms[k] = 0, n[k] = 0;
   }
+  // start of a propagate: the per-step bookkeeping covers this call only
+  void begin() {
+    step_iters.clear();
+    cur_step = cur_iter = 0;
+  }
   ~GmmProfiler() {
     for (auto& r : recs) pool.push_back(r.a), pool.push_back(r.b);
     for (hipEvent_t e : pool)
@@ -291,6 +296,31 @@ int ensure_workspace(gmm_plan_s* P, int cap) {
   return GMM_OK;
 }
 
+// Device buffers one nonlinear evaluation works in: the plan's own workspace,
+// or a batch's buffers.
+struct EvalWs {
+  void* work = nullptr;             // [cap][N][Nt] field rows
+  void* Bp = nullptr;               // pair rows / Y' (layout of bp_bytes)
+  void* Y = nullptr;                // rank-r route: [cap][RQ][Nt]
+  cplx<double>* gpart = nullptr;    // gain / coupling: pair-integral partials
+  cplx<double>* Mg = nullptr;       // gain / coupling: per-sub-step matrices
+  int cap = 0, gain_cap = 0;        // sub-steps the buffers hold
+  size_t plane_words = 0;           // BF16 planes: words per plane
+};
+
+EvalWs plan_ws(const gmm_plan_s* P) {
+  EvalWs w;
+  w.work = P->work;
+  w.Bp = P->Bp;
+  w.Y = P->Y;
+  w.gpart = P->gpart;
+  w.Mg = P->Mg;
+  w.cap = P->cap;
+  w.gain_cap = P->gain_cap;
+  w.plane_words = bp_plane_words(P);
+  return w;
+}
+
 // ---------------------------------------------------------------------------
 // Typed sequencing of one nonlinear evaluation and one iteration.
 template <typename T>
@@ -298,47 +328,18 @@ struct Runner {
   gmm_plan_s* P;
   const cplx<T>* tw() const { return (const cplx<T>*)P->tw; }
 
-  // out[c] = N~[ exp(D z_{j0+c}) psi_c ] * exp(-D z_{j0+c}) for c < count.
-  // psi_c starts at psi + c * jrows * Nt: jrows = N (one field per sub-step)
-  // or 0 (every sub-step reads the same field).  Field rows go through
-  // `work`; `out` may be `work` itself.
-  // part 0: the whole evaluation; part 1: its first half (transforms to time, gain matrices, pair rows or
-  // Y = V B and the Raman convolution); part 2: the rest (contraction, transforms back, gain term).  The MPA
-  // driver queues the halves separately so that it can wait for a stop flag in the middle of an iteration.
-  int eval(const cplx<T>* psi, long jrows, int count, int j0, double dz, cplx<T>* out, const Ctrl* ctrl,
-           int part = 0) {
-    const bool doA = part != 2, doB = part != 1;
-    if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
-    if (count > P->cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
-    cplx<T>* W = (cplx<T>*)P->work;
-    const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
-    // coupled linear operator: psi is in the eigenbasis; the modes are U (exp(i lam z) psi)
-    const bool mix = P->cpl_exact && E != nullptr;
-    if (mix && doA) {
-      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::mode_mix(false, psi, jrows, W, (const cplx<T>*)P->Uc, E, j0, P->N,
-                                                      P->nt, count, ctrl, P->stream));
-      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, W, P->N, W, nullptr, P->N, count, j0, tw(),
-                                                           ctrl, P->stream));
-    } else if (doA) {
-      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
-                                                           P->stream));
-    }
-    const bool linear_terms = P->gain_on || P->coupling_on;
-    if (linear_terms && doA) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
-      if (count > P->gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
-      if (P->gain_on && P->inv_Isat != 0.0)
-        GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, P->gpart, P->N, P->nt, count, ctrl, P->stream));
-      GMM_LAUNCH(P, GMM_PROF_GAIN,
-                 gmm::launch_gain_matrix(P->gpart, gmm::gain_partials(P->nt), P->SRd,
-                                         P->gain_on ? P->gvec : nullptr, P->inv_Isat, P->prm.dt,
-                                         P->coupling_on ? P->Kc : nullptr, P->Mg, P->N, count, ctrl, P->stream));
-    }
+  // The route-specific middle of one evaluation over `count` field rows of
+  // ws.work (time domain in, NL(t) out in place): pair rows or Y = V B, the Raman
+  // convolution, the contraction and the mode projection.  doA / doB: the
+  // halves before / from the contraction.
+  int mid(int count, const EvalWs& ws, const Ctrl* ctrl, bool doA, bool doB) {
+    cplx<T>* W = (cplx<T>*)ws.work;
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
       bool os_done = false;
       if constexpr (std::is_same<T, float>::value) {
         if (P->os_lh) {  // Raman on, short h_R: overlap-save segments
           if (doA)
-            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_dense_os(W, (float*)P->Bp, P->pairs, P->N, P->Np, count,
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_dense_os(W, (float*)ws.Bp, P->pairs, P->N, P->Np, count,
                                                                      P->KD, P->nt, P->os_lh, P->os_v,
                                                                      (const cplx<float>*)P->Gos,
                                                                      (const cplx<float>*)P->twos, ctrl, P->stream));
@@ -346,23 +347,23 @@ struct Runner {
         }
       }
       if (doA && !os_done)
-        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np,
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_dense(P->logn, P->raman, W, (T*)ws.Bp, P->pairs, P->N, P->Np,
                                                            count, P->KD, (const cplx<T>*)P->Hs, tw(), ctrl,
                                                            P->stream));
       bool done = false;
       if constexpr (std::is_same<T, float>::value) {
         if (P->bf16 && doB) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT,
-                     gmm::launch_contract_dense_bf16(P->Ghi, P->Glo, (const float*)P->Bp, W, P->N, P->KD, P->KD32,
+                     gmm::launch_contract_dense_bf16(P->Ghi, P->Glo, (const float*)ws.Bp, W, P->N, P->KD, P->KD32,
                                                      P->nt, count, ctrl, P->stream));
         }
         done = P->bf16;
       }
       if (!done && doB)
-        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)P->Bp, W, P->N, P->KD,
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract_dense((const T*)P->G, (const T*)ws.Bp, W, P->N, P->KD,
                                                                    P->rows_pad, P->nt, count, ctrl, P->stream));
     } else if (P->factored) {  // Y = V B; Y' = g * Y (r rows); C = U Y' + projection
-      T* Y = (T*)P->Y;
+      T* Y = (T*)ws.Y;
       if constexpr (std::is_same<T, float>::value) {
         if (doA)
           GMM_LAUNCH(P, GMM_PROF_PROJECT,
@@ -375,8 +376,8 @@ struct Runner {
       const int R = P->rank + (P->rank & 1);
       if constexpr (std::is_same<T, float>::value) {
         if (P->bf16) {
-          uint32_t* bhi = (uint32_t*)P->Bp;
-          uint32_t* blo = bhi + bp_plane_words(P);
+          uint32_t* bhi = (uint32_t*)ws.Bp;
+          uint32_t* blo = bhi + ws.plane_words;
           if (P->os_lh && doA)
             GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_conv_os(Y, nullptr, bhi, blo, R, P->rq, count, P->nt, P->os_lh,
                                                               P->os_v, (const cplx<float>*)P->Gos,
@@ -392,25 +393,25 @@ struct Runner {
       if (!P->bf16) {
         const bool os_done = P->os_lh != 0;
         if (os_done && doA)
-          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv_os(Y, (T*)P->Bp, R, P->rq, count, P->nt, P->os_lh, P->os_v,
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv_os(Y, (T*)ws.Bp, R, P->rq, count, P->nt, P->os_lh, P->os_v,
                                                          (const cplx<T>*)P->Gos, (const cplx<T>*)P->twos, ctrl,
                                                          P->stream));
         if (!os_done && doA)
-          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)P->Bp, R, P->rq, count,
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)ws.Bp, R, P->rq, count,
                                                         (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
         if constexpr (std::is_same<T, float>::value) {
           if (doB)
-            GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, P->Bp, nullptr,
+            GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, ws.Bp, nullptr,
                                                                      W, P->N, P->rq, P->nt, count, ctrl, P->stream));
         } else if (doB) {
-          GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)P->Bp, W,
+          GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)ws.Bp, W,
                                                                P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream));
         }
       }
     } else if constexpr (std::is_same<T, float>::value) {
       if (P->bf16) {  // packed route, BF16 split
-        uint32_t* bhi = (uint32_t*)P->Bp;
-        uint32_t* blo = bhi + bp_plane_words(P);
+        uint32_t* bhi = (uint32_t*)ws.Bp;
+        uint32_t* blo = bhi + ws.plane_words;
         if (doA && P->os_lh)
           GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_os(W, nullptr, bhi, blo, P->pairs, P->N, P->Np, count, P->nt,
                                                              P->os_lh, P->os_v, (const cplx<float>*)P->Gos,
@@ -426,15 +427,58 @@ struct Runner {
     if (!P->bf16 && !P->factored && !P->dense) {
       const bool os_done = P->os_lh != 0;
       if (os_done && doA)
-        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_os(W, (T*)P->Bp, P->pairs, P->N, P->Np, count, P->nt, P->os_lh,
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs_os(W, (T*)ws.Bp, P->pairs, P->N, P->Np, count, P->nt, P->os_lh,
                                                         P->os_v, (const cplx<T>*)P->Gos, (const cplx<T>*)P->twos, ctrl,
                                                         P->stream));
       if (doA && !os_done)
-        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)P->Bp, P->pairs, P->N, P->Np, count,
+        GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::pairs(P->logn, P->raman, W, (T*)ws.Bp, P->pairs, P->N, P->Np, count,
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
       if (doB)
-        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)P->Bp, W, P->pidx,
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)ws.Bp, W, P->pidx,
                                                            P->N, P->Np, P->nt, count, ctrl, P->stream));
+    }
+    return GMM_OK;
+  }
+
+  // out[c] = N~[ exp(D z_{j0+c}) psi_c ] * exp(-D z_{j0+c}) for c < count.
+  // psi_c starts at psi + c * jrows * Nt: jrows = N (one field per sub-step)
+  // or 0 (every sub-step reads the same field).  Field rows go through
+  // `work`; `out` may be `work` itself.
+  // part 0: the whole evaluation; part 1: its first half (transforms to time, gain matrices, pair rows or
+  // Y = V B and the Raman convolution); part 2: the rest (contraction, transforms back, gain term).  The MPA
+  // driver queues the halves separately so that it can wait for a stop flag in the middle of an iteration.
+  int eval(const cplx<T>* psi, long jrows, int count, int j0, double dz, cplx<T>* out, const Ctrl* ctrl,
+           int part = 0, const EvalWs* wsp = nullptr) {
+    const EvalWs ws = wsp ? *wsp : plan_ws(P);
+    const bool doA = part != 2, doB = part != 1;
+    if (jrows != 0 && jrows != P->N) return fail(GMM_ERR_ARG, "internal: sub-step stride must be 0 or N rows");
+    if (count > ws.cap) return fail(GMM_ERR_ARG, "internal: workspace smaller than the sub-step count");
+    cplx<T>* W = (cplx<T>*)ws.work;
+    const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
+    // coupled linear operator: psi is in the eigenbasis; the modes are U (exp(i lam z) psi)
+    const bool mix = P->cpl_exact && E != nullptr;
+    if (mix && doA) {
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::mode_mix(false, psi, jrows, W, (const cplx<T>*)P->Uc, E, j0, P->N,
+                                                      P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, W, P->N, W, nullptr, P->N, count, j0, tw(),
+                                                           ctrl, P->stream));
+    } else if (doA) {
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
+                                                           P->stream));
+    }
+    const bool linear_terms = P->gain_on || P->coupling_on;
+    if (linear_terms && doA) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
+      if (count > ws.gain_cap) return fail(GMM_ERR_ARG, "internal: gain workspace smaller than the sub-step count");
+      if (P->gain_on && P->inv_Isat != 0.0)
+        GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::pair_integrals(W, ws.gpart, P->N, P->nt, count, ctrl, P->stream));
+      GMM_LAUNCH(P, GMM_PROF_GAIN,
+                 gmm::launch_gain_matrix(ws.gpart, gmm::gain_partials(P->nt), P->SRd,
+                                         P->gain_on ? P->gvec : nullptr, P->inv_Isat, P->prm.dt,
+                                         P->coupling_on ? P->Kc : nullptr, ws.Mg, P->N, count, ctrl, P->stream));
+    }
+    {
+      const int rc_mid = mid(count, ws, ctrl, doA, doB);
+      if (rc_mid) return rc_mid;
     }
     if (!doB) return GMM_OK;
     GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, mix ? nullptr : E, P->N, count, j0,
@@ -444,7 +488,7 @@ struct Runner {
       GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::mode_mix(true, out, P->N, out, (const cplx<T>*)P->Uc, E, j0, P->N,
                                                          P->nt, count, ctrl, P->stream));
     if (linear_terms)
-      GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::gain_add(psi, jrows, E, j0, P->Mg, out, P->N, P->nt, count, ctrl,
+      GMM_LAUNCH(P, GMM_PROF_GAIN, Launch<T>::gain_add(psi, jrows, E, j0, ws.Mg, out, P->N, P->nt, count, ctrl,
                                                        P->stream));
     return GMM_OK;
   }
@@ -517,6 +561,7 @@ struct Runner {
                                                                             : (long)std::ceil(r);
     if (n_small < 1) n_small = 1;
     const double dz = L / (double)n_small;
+    P->prof.begin();
     int rc = ensure_workspace(P, M + 1);  // the first iteration also evaluates sub-step 0
     if (rc) return rc;
     if ((rc = ensure_gain_workspace(P, M + 1))) return rc;
@@ -572,7 +617,7 @@ struct Runner {
       }
       const Ctrl c = *P->h_ctrl;
       P->prof.cur_iter = 0;
-      P->prof.step_iters.push_back(c.iters);
+      if (P->prof.on) P->prof.step_iters.push_back(c.iters);
       if (c.status == 2) return fail(GMM_ERR_DIVERGED, "non-finite relative change in the MPA iteration");
       if (c.status == 1) {
         s.nonconverged_steps++;
@@ -612,6 +657,7 @@ struct Runner {
                                                                             : (long)std::ceil(r);
     if (n_small < 1) n_small = 1;
     const double h = L / (double)n_small;
+    P->prof.begin();
     int rc = ensure_workspace(P, 6);  // AI, k1..k4, X in the sub-step rows
     if (rc) return rc;
     if ((rc = ensure_gain_workspace(P, 1))) return rc;
@@ -659,6 +705,7 @@ struct Runner {
     }
     return rc;
   }
+
 };
 
 template <typename T>
@@ -1252,6 +1299,319 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   return GMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched propagations of one plan (continuous batching): S slots, each an
+// independent propagation with its own field, length and step, advance in
+// rounds.  A round queues one MPA iteration for every running slot: the
+// sub-step rows of all of them go through one launch per kernel kind (their
+// field rows packed into one work buffer), then the trapezoid and the norm run
+// per slot, and the host reads all control blocks back once.  A slot whose
+// large step converged is closed at the start of the next round and starts its
+// next large step there; a slot that reached its length gets its final
+// transform and frees up, and a new propagation can be admitted into it while
+// the others keep running.  Per slot the kernels compute exactly what
+// gmm_propagate computes, in the same order.
+struct BatchSlotState {
+  int state = 0;  // 0 free, 1 running, 2 final transform queued
+  long n_small = 0, done = 0;
+  double dz = 0.0, E_dz = std::nan("");
+  int m = 0;
+  bool first = true, need_close = false;
+  void* Aout = nullptr;
+  long long tag = 0;
+  gmm_stats st{};
+  int status = GMM_OK;
+};
+
+}  // namespace
+
+struct gmm_batch_s {
+  gmm_plan_s* P = nullptr;
+  int S = 0, M = 0, nblk = 0;
+  void *psi0 = nullptr, *I0 = nullptr, *psi = nullptr, *E = nullptr, *work = nullptr, *Bp = nullptr, *Y = nullptr;
+  double* partials = nullptr;  // [S][nblk][2]
+  double* spec = nullptr;      // [S][2][nblk][2]: spectral sums at admission (0) and at the end (1)
+  gmm::Ctrl* ctrl = nullptr;   // [S]
+  gmm::BatchRow* rows_d = nullptr;    // [S (M + 1)]
+  gmm::BatchSlot* slots_d = nullptr;  // [2 S]: iterating slots, then closing slots
+  gmm::BatchRow* rows_h = nullptr;    // pinned mirrors
+  gmm::BatchSlot* slots_h = nullptr;
+  gmm::Ctrl* ctrl_h = nullptr;
+  double* spec_h = nullptr;
+  std::vector<BatchSlotState> slot;
+  std::vector<int> round;       // slots iterating in the queued round
+  bool pending = false, spec_dirty = false;
+  long long bytes = 0;
+};
+
+namespace {
+
+void batch_free(gmm_batch_s* B) {
+  if (!B) return;
+  for (void* p : {B->psi0, B->I0, B->psi, B->E, B->work, B->Bp, B->Y, (void*)B->partials, (void*)B->spec,
+                  (void*)B->ctrl, (void*)B->rows_d, (void*)B->slots_d})
+    if (p) (void)hipFree(p);
+  for (void* p : {(void*)B->rows_h, (void*)B->slots_h, (void*)B->ctrl_h, (void*)B->spec_h})
+    if (p) (void)hipHostFree(p);
+  delete B;
+}
+
+template <typename T>
+struct BatchRunner {
+  gmm_batch_s* B;
+  gmm_plan_s* P;
+  size_t nn() const { return (size_t)P->N * P->nt; }
+  cplx<T>* at(void* base, size_t row) const { return (cplx<T>*)base + row * nn(); }
+  const cplx<T>* tw() const { return (const cplx<T>*)P->tw; }
+
+  int spec_sums_into(int s, int which) {
+    double* dst = B->spec + ((size_t)s * 2 + which) * 2 * B->nblk;
+    GMM_HIP(Launch<T>::spec_sums(at(B->psi0, s), P->nt, (long)nn(), P->domega, P->prm.omega0, dst, P->stream));
+    B->spec_dirty = true;
+    return GMM_OK;
+  }
+  void spec_read(int s, int which, double* energy, double* photons) const {
+    const double* h = B->spec_h + ((size_t)s * 2 + which) * 2 * B->nblk;
+    double a = 0, b = 0;
+    for (int i = 0; i < B->nblk; ++i) {
+      a += h[2 * i];
+      b += h[2 * i + 1];
+    }
+    *energy = a * P->nt * P->prm.dt;
+    *photons = b;
+  }
+
+  int submit(const void* A0, double L, double dz_req, void* Aout, long long tag) {
+    int s = -1;
+    for (int i = 0; i < B->S; ++i)
+      if (B->slot[i].state == 0) {
+        s = i;
+        break;
+      }
+    if (s < 0) return fail(GMM_ERR_BUSY, "no free slot in the batch");
+    const double r = L / dz_req;
+    long n_small = (std::fabs(r - std::round(r)) < 1e-9 * std::max(1.0, r)) ? (long)std::llround(r)
+                                                                            : (long)std::ceil(r);
+    if (n_small < 1) n_small = 1;
+    BatchSlotState& q = B->slot[s];
+    const double dz = L / (double)n_small;
+    GMM_HIP(Launch<T>::fft_rows(P->logn, +1, (const cplx<T>*)A0, at(B->psi0, s), (T)(1.0 / P->nt), P->N, tw(),
+                                P->stream));
+    int rc = spec_sums_into(s, 0);
+    if (rc) return rc;
+    if (!(q.E_dz == dz)) {
+      GMM_HIP(Launch<T>::phase_table(at(B->E, (size_t)s * (B->M + 1)), P->coef, P->nb, P->N, P->nt, B->M + 1, dz,
+                                     P->domega, P->stream));
+      q.E_dz = dz;
+    }
+    GMM_HIP(gmm::launch_ctrl_reset(B->ctrl + s, P->stream));
+    q.state = 1;
+    q.n_small = n_small;
+    q.done = 0;
+    q.dz = dz;
+    q.m = (int)std::min<long>(B->M, n_small);
+    q.first = true;
+    q.need_close = false;
+    q.Aout = Aout;
+    q.tag = tag;
+    q.st = gmm_stats{};
+    q.st.dz_used = dz;
+    q.status = GMM_OK;
+    return s;
+  }
+
+  int launch() {
+    const size_t n = nn();
+    const int S = B->S, M = B->M;
+    // 1. close the slots whose large step converged in the last round
+    int nclose = 0;
+    std::vector<int> closing;
+    for (int s = 0; s < S; ++s) {
+      BatchSlotState& q = B->slot[s];
+      if (q.state != 1 || !q.need_close) continue;
+      gmm::BatchSlot& d = B->slots_h[S + nclose++];
+      d = gmm::BatchSlot{};
+      d.psi = at(B->psi, (size_t)s * M);
+      d.dst = at(B->psi0, s);
+      d.Em = at(B->E, (size_t)s * (M + 1) + q.m);
+      d.ctrl = B->ctrl + s;
+      d.m = q.m;
+      closing.push_back(s);
+    }
+    // 2. rows of the slots that iterate in this round
+    B->round.clear();
+    int R = 0, ns = 0;
+    for (int s = 0; s < S; ++s) {
+      BatchSlotState& q = B->slot[s];
+      if (q.state != 1) continue;
+      if (q.need_close) {  // the close below finishes this large step
+        q.done += q.m;
+        q.st.large_steps++;
+        q.st.small_steps += q.m;
+        q.need_close = false;
+        if (q.done >= q.n_small) {
+          q.state = 2;  // final transform queued after the close
+          continue;
+        }
+        q.first = true;
+        q.m = (int)std::min<long>(M, q.n_small - q.done);
+      }
+      const int o = R;
+      if (q.first)
+        for (int j = 0; j <= q.m; ++j) B->rows_h[R++] = gmm::BatchRow{s, -1, j, 0};
+      else
+        for (int j = 1; j <= q.m; ++j) B->rows_h[R++] = gmm::BatchRow{s, j - 1, j, 0};
+      gmm::BatchSlot& d = B->slots_h[ns++];
+      d = gmm::BatchSlot{};
+      d.psi0 = at(B->psi0, s);
+      d.I0 = q.first ? (const void*)at(B->work, o) : (const void*)at(B->I0, s);
+      d.I = at(B->work, q.first ? o + 1 : o);
+      d.psi = at(B->psi, (size_t)s * M);
+      d.I0_keep = at(B->I0, s);
+      d.partials = B->partials + (size_t)s * 2 * B->nblk;
+      d.ctrl = B->ctrl + s;
+      d.dz = q.dz;
+      d.first = q.first ? 1 : 0;
+      d.m = q.m;
+      B->round.push_back(s);
+    }
+    if (R > 0) GMM_HIP(hipMemcpyAsync(B->rows_d, B->rows_h, (size_t)R * sizeof(gmm::BatchRow),
+                                      hipMemcpyHostToDevice, P->stream));
+    if (ns + nclose > 0)
+      GMM_HIP(hipMemcpyAsync(B->slots_d, B->slots_h, (size_t)2 * S * sizeof(gmm::BatchSlot), hipMemcpyHostToDevice,
+                             P->stream));
+    GMM_HIP(Launch<T>::close_b(B->slots_d + S, nclose, (long)n, P->stream));
+    for (int s : closing) {  // slots at their length: spectral sums and the transform back to time
+      BatchSlotState& q = B->slot[s];
+      if (q.state != 2) continue;
+      int rc = spec_sums_into(s, 1);
+      if (rc) return rc;
+      GMM_HIP(Launch<T>::fft_rows(P->logn, -1, at(B->psi0, s), (cplx<T>*)q.Aout, (T)1, P->N, tw(), P->stream));
+    }
+    if (R > 0) {
+      EvalWs ws;
+      ws.work = B->work;
+      ws.Bp = B->Bp;
+      ws.Y = B->Y;
+      ws.cap = S * (M + 1);
+      ws.plane_words = (size_t)ws.cap * gmm::kBf16Kpad * P->nt / 2;
+      cplx<T>* W = (cplx<T>*)B->work;
+      GMM_HIP(Launch<T>::phase_to_time_b(P->logn, B->rows_d, (const cplx<T>*)B->psi0, (const cplx<T>*)B->psi,
+                                         (const cplx<T>*)B->E, W, P->N, R, M, tw(), P->stream));
+      const bool prof_on = P->prof.on;  // per-kernel events are for gmm_propagate
+      P->prof.on = false;
+      const int rc = Runner<T>{P}.mid(R, ws, nullptr, true, true);
+      P->prof.on = prof_on;
+      if (rc) return rc;
+      GMM_HIP(Launch<T>::spectral_out_b(P->logn, B->rows_d, W, (const cplx<T>*)B->E, P->N, R, M, P->domega,
+                                        P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(),
+                                        P->stream));
+      GMM_HIP(Launch<T>::trapz_b(B->slots_d, ns, (long)n, P->stream));
+      GMM_HIP(gmm::launch_norm_final_b(B->slots_d, ns, B->nblk, P->prm.tol, P->prm.fixed_iters, P->prm.max_iter,
+                                       P->stream));
+    }
+    GMM_HIP(hipMemcpyAsync(B->ctrl_h, B->ctrl, (size_t)S * sizeof(gmm::Ctrl), hipMemcpyDeviceToHost, P->stream));
+    if (B->spec_dirty) {
+      GMM_HIP(hipMemcpyAsync(B->spec_h, B->spec, (size_t)S * 4 * B->nblk * sizeof(double), hipMemcpyDeviceToHost,
+                             P->stream));
+      B->spec_dirty = false;
+    }
+    B->pending = true;
+    return GMM_OK;
+  }
+
+  int wait(long long* tags, int* status, gmm_stats* stats, int max_done, int* n_done) {
+    *n_done = 0;
+    if (!B->pending) return GMM_OK;
+    GMM_HIP(hipStreamSynchronize(P->stream));
+    B->pending = false;
+    for (int s : B->round) {
+      BatchSlotState& q = B->slot[s];
+      const gmm::Ctrl c = B->ctrl_h[s];
+      if (c.status == 2) {  // non-finite relative change: report and free the slot
+        q.status = GMM_ERR_DIVERGED;
+        q.state = 2;
+        q.st.last_eps = c.eps;
+        continue;
+      }
+      if (c.done) {
+        if (c.status == 1) {
+          q.st.nonconverged_steps++;
+          q.status = GMM_NOT_CONVERGED;
+        }
+        q.st.iterations += c.iters;
+        q.st.evaluations += 1 + (long long)c.iters * q.m;
+        if (c.iters > q.st.max_iters_seen) q.st.max_iters_seen = c.iters;
+        q.st.last_eps = c.eps;
+        q.need_close = true;
+      } else {
+        q.first = false;
+      }
+    }
+    // report the slots whose final transform has run (or that failed), and free them
+    for (int s = 0; s < B->S; ++s) {
+      BatchSlotState& q = B->slot[s];
+      if (q.state != 2) continue;
+      const bool in_round = std::find(B->round.begin(), B->round.end(), s) != B->round.end();
+      if (in_round && q.status != GMM_ERR_DIVERGED) continue;  // finished transform is queued next round
+      if (*n_done >= max_done) break;
+      if (q.status != GMM_ERR_DIVERGED) {
+        spec_read(s, 0, &q.st.energy_in, &q.st.photons_in);
+        spec_read(s, 1, &q.st.energy_out, &q.st.photons_out);
+      }
+      tags[*n_done] = q.tag;
+      if (status) status[*n_done] = q.status;
+      if (stats) stats[*n_done] = q.st;
+      ++*n_done;
+      q.state = 0;
+    }
+    int running = 0;
+    for (const auto& q : B->slot) running += q.state != 0;
+    return running;
+  }
+};
+
+int batch_create(gmm_batch* out, gmm_plan_s* P, int slots, int M) {
+  if (P->gain_on || P->coupling_on || P->cpl_exact)
+    return fail(GMM_ERR_UNSUPPORTED, "batched propagation without the gain and coupling terms only");
+  gmm_batch_s* B = new gmm_batch_s();
+  B->P = P;
+  B->S = slots;
+  B->M = M;
+  const size_t nn = (size_t)P->N * P->nt, fb = field_bytes(P);
+  B->nblk = gmm::trapz_blocks((long)nn);
+  const int cap = slots * (M + 1);
+  long long* c = &B->bytes;
+  int rc;
+  auto bail = [&](int code) {
+    batch_free(B);
+    return code;
+  };
+  if ((rc = dev_alloc(c, &B->psi0, fb * slots)) || (rc = dev_alloc(c, &B->I0, fb * slots)) ||
+      (rc = dev_alloc(c, &B->psi, fb * slots * M)) || (rc = dev_alloc(c, &B->E, fb * slots * (M + 1))) ||
+      (rc = dev_alloc(c, &B->work, fb * cap)) || (rc = dev_alloc(c, &B->Bp, bp_bytes(P, cap))) ||
+      (P->factored && (rc = dev_alloc(c, &B->Y, (size_t)cap * P->rq * P->nt * P->esz))) ||
+      (rc = dev_alloc(c, &B->partials, (size_t)slots * 2 * B->nblk * sizeof(double))) ||
+      (rc = dev_alloc(c, &B->spec, (size_t)slots * 4 * B->nblk * sizeof(double))) ||
+      (rc = dev_alloc(c, &B->ctrl, (size_t)slots * sizeof(gmm::Ctrl))) ||
+      (rc = dev_alloc(c, &B->rows_d, (size_t)cap * sizeof(gmm::BatchRow))) ||
+      (rc = dev_alloc(c, &B->slots_d, (size_t)2 * slots * sizeof(gmm::BatchSlot))))
+    return bail(rc);
+  if (hipMemset(B->Bp, 0, bp_bytes(P, cap)) != hipSuccess ||
+      hipMemset(B->ctrl, 0, (size_t)slots * sizeof(gmm::Ctrl)) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "hipMemset of the batch buffers failed"));
+  if (hipHostMalloc((void**)&B->rows_h, (size_t)cap * sizeof(gmm::BatchRow), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&B->slots_h, (size_t)2 * slots * sizeof(gmm::BatchSlot), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&B->ctrl_h, (size_t)slots * sizeof(gmm::Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&B->spec_h, (size_t)slots * 4 * B->nblk * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess)
+    return bail(fail(GMM_ERR_NOMEM, "pinned host allocation failed"));
+  B->slot.assign(slots, BatchSlotState{});
+  *out = B;
+  return GMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1413,6 +1773,74 @@ int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out) {
   if (At == out) return fail(GMM_ERR_ARG, "out must not alias At");
   return plan->fp64 ? Runner<double>{plan}.nonlinear(At, count, out) : Runner<float>{plan}.nonlinear(At, count, out);
 }
+
+int gmm_batch_create(gmm_batch* out, gmm_plan plan, int slots, int M) {
+  if (!out) return fail(GMM_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  if (slots < 1 || slots > 4096) return fail(GMM_ERR_ARG, "slots must be 1..4096");
+  if (M < 1 || M > 1024) return fail(GMM_ERR_ARG, "M must be 1..1024");
+  try {
+    const int rc = batch_create(out, plan, slots, M);
+    if (rc == GMM_OK) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_batch_submit(gmm_batch b, const void* A0, double L, double dz, void* Aout, long long tag) {
+  if (!b || !A0 || !Aout) return fail(GMM_ERR_ARG, "null argument");
+  if (!(L > 0) || !(dz > 0) || !std::isfinite(L) || !std::isfinite(dz)) return fail(GMM_ERR_ARG, "L and dz must be > 0");
+  if (L / dz > 1e12) return fail(GMM_ERR_ARG, "too many small steps");
+  gmm_plan_s* P = b->P;
+  if (P->gain_on || P->coupling_on || P->cpl_exact)
+    return fail(GMM_ERR_UNSUPPORTED, "batched propagation without the gain and coupling terms only");
+  try {
+    const int rc = P->fp64 ? BatchRunner<double>{b, P}.submit(A0, L, dz, Aout, tag)
+                           : BatchRunner<float>{b, P}.submit(A0, L, dz, Aout, tag);
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_batch_launch(gmm_batch b) {
+  if (!b) return fail(GMM_ERR_ARG, "null batch");
+  if (b->pending) return fail(GMM_ERR_ARG, "a round is already queued: call gmm_batch_wait first");
+  gmm_plan_s* P = b->P;
+  if (P->gain_on || P->coupling_on || P->cpl_exact)
+    return fail(GMM_ERR_UNSUPPORTED, "batched propagation without the gain and coupling terms only");
+  try {
+    const int rc = P->fp64 ? BatchRunner<double>{b, P}.launch() : BatchRunner<float>{b, P}.launch();
+    if (rc == GMM_OK) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_batch_wait(gmm_batch b, long long* tags, int* status, gmm_stats* stats, int max_done, int* n_done) {
+  if (!b || !n_done || (max_done > 0 && !tags)) return fail(GMM_ERR_ARG, "null argument");
+  if (max_done < b->S) return fail(GMM_ERR_ARG, "max_done must be at least the slot count");
+  try {
+    const int rc = b->P->fp64 ? BatchRunner<double>{b, b->P}.wait(tags, status, stats, max_done, n_done)
+                              : BatchRunner<float>{b, b->P}.wait(tags, status, stats, max_done, n_done);
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_batch_destroy(gmm_batch b) {
+  if (b && b->pending) (void)hipStreamSynchronize(b->P->stream);
+  batch_free(b);
+  return GMM_OK;
+}
+
+long long gmm_batch_device_bytes(gmm_batch b) { return b ? b->bytes : 0; }
 
 int gmm_plan_destroy(gmm_plan plan) {
   destroy(plan);

@@ -24,6 +24,7 @@ GMM_ERR_TENSOR = -3
 GMM_ERR_HIP = -4
 GMM_ERR_UNSUPPORTED = -5
 GMM_ERR_DIVERGED = -6
+GMM_ERR_BUSY = -7
 GMM_FP64 = 0
 GMM_FP32 = 1
 GMM_BF16X3 = 2
@@ -31,7 +32,8 @@ GMM_BF16X3 = 2
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_plan_set_gain",
            "gmm_plan_set_coupling", "gmm_plan_set_coupling_exact", "gmm_nonlinear",
            "gmm_plan_destroy", "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable",
-           "gmm_profile_read")
+           "gmm_profile_read", "gmm_batch_create", "gmm_batch_submit", "gmm_batch_launch", "gmm_batch_wait",
+           "gmm_batch_destroy", "gmm_batch_device_bytes")
 PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project",
                  "gain")
 
@@ -84,6 +86,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_nonlinear.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
     lib.gmm_plan_destroy.restype = ci
+    lib.gmm_batch_create.argtypes = [ctypes.POINTER(vp), vp, ci, ci]
+    lib.gmm_batch_create.restype = ci
+    lib.gmm_batch_submit.argtypes = [vp, vp, dbl, dbl, vp, ctypes.c_longlong]
+    lib.gmm_batch_submit.restype = ci
+    lib.gmm_batch_launch.argtypes = [vp]
+    lib.gmm_batch_launch.restype = ci
+    lib.gmm_batch_wait.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ci),
+                                   ctypes.POINTER(gmm_stats), ci, ctypes.POINTER(ci)]
+    lib.gmm_batch_wait.restype = ci
+    lib.gmm_batch_destroy.argtypes = [vp]
+    lib.gmm_batch_destroy.restype = ci
+    lib.gmm_batch_device_bytes.argtypes = [vp]
+    lib.gmm_batch_device_bytes.restype = ctypes.c_longlong
     lib.gmm_last_error.argtypes = []
     lib.gmm_last_error.restype = ctypes.c_char_p
     lib.gmm_plan_device_bytes.argtypes = [vp]
@@ -290,3 +305,107 @@ def plan_from_workload(w, precision: str = "fp64", **kw) -> Plan:
     """Plan for a synthetic workload object (see paper_1708_05324_amd.synth)."""
     return Plan(w.betas, w.S, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,
                 self_steepening=w.self_steepening, precision=precision, **kw)
+
+
+class Batch:
+    """Batched propagations of one plan with continuous admission
+    (gmm_batch_*): up to `slots` propagations advance together in rounds; a
+    completed one frees its slot for the next submission."""
+
+    def __init__(self, plan: Plan, slots: int, M: int):
+        self.plan = plan
+        self.lib = plan.lib
+        self.slots = int(slots)
+        self.M = int(M)
+        handle = ctypes.c_void_p()
+        _check(self.lib.gmm_batch_create(ctypes.byref(handle), plan.handle, self.slots, self.M))
+        self.handle = handle
+        self._keep = {}            # tag -> (A0, out): device buffers referenced by queued work
+        self._tags = (ctypes.c_longlong * self.slots)()
+        self._status = (ctypes.c_int * self.slots)()
+        self._stats = (gmm_stats * self.slots)()
+
+    def submit(self, A0, L: float, dz: float, tag: int, out=None):
+        """Admit one propagation; returns (slot, out), or None when every slot is taken."""
+        import torch
+        self.plan._check_field(A0)
+        if tuple(A0.shape) != (self.plan.n_modes, self.plan.nt):
+            raise ValueError("A0 must be [N][Nt]")
+        if out is None:
+            out = torch.empty_like(A0)
+        rc = self.lib.gmm_batch_submit(self.handle, ctypes.c_void_p(A0.data_ptr()), float(L), float(dz),
+                                       ctypes.c_void_p(out.data_ptr()), int(tag))
+        if rc == GMM_ERR_BUSY:
+            return None
+        if rc < 0:
+            _check(rc)
+        self._keep[int(tag)] = (A0, out)
+        return rc, out
+
+    def launch(self):
+        _check(self.lib.gmm_batch_launch(self.handle))
+
+    def wait(self):
+        """Wait for the queued round: (propagations still running, completed
+        [(tag, return code, stats dict, output tensor)])."""
+        n = ctypes.c_int()
+        rc = self.lib.gmm_batch_wait(self.handle, self._tags, self._status, self._stats, self.slots,
+                                     ctypes.byref(n))
+        if rc < 0:
+            _check(rc)
+        done = []
+        for i in range(n.value):
+            tag = int(self._tags[i])
+            _, out = self._keep.pop(tag)
+            done.append((tag, int(self._status[i]), self._stats[i].as_dict(), out))
+        return rc, done
+
+    def device_bytes(self) -> int:
+        return int(self.lib.gmm_batch_device_bytes(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.gmm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_batches(batches, jobs):
+    """Drive several batches (each with its own plan, ideally on its own stream)
+    until every job is done, keeping their slots full: jobs is a list of
+    (batch index, A0, L, dz, tag).  Rounds of all batches are queued before
+    any is waited for, so their work overlaps on the device.  Returns
+    {tag: (return code, stats, output)}."""
+    pending = [list() for _ in batches]
+    for j in jobs:
+        pending[j[0]].append(j)
+    for q in pending:
+        q.reverse()
+    results = {}
+    active = [0] * len(batches)
+    while True:
+        any_work = False
+        for b, batch in enumerate(batches):
+            while pending[b]:
+                _, A0, L, dz, tag = pending[b][-1]
+                if batch.submit(A0, L, dz, tag) is None:
+                    break
+                pending[b].pop()
+                active[b] += 1
+            if active[b] > 0:
+                batch.launch()
+                any_work = True
+        if not any_work:
+            break
+        for b, batch in enumerate(batches):
+            if active[b] > 0:
+                running, done = batch.wait()
+                active[b] = running
+                for tag, rc, st, out in done:
+                    results[tag] = (rc, st, out)
+    return results
