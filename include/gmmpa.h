@@ -207,6 +207,34 @@ int gmm_plan_set_coupling_exact(gmm_plan plan, const double* Q, int q_complex);
 int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out);
 
 /*
+ * gmm_nonlinear_noalloc - gmm_nonlinear for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and result as gmm_nonlinear
+ * (bit for bit), but the workspace of the evaluation comes from a static
+ * device array of GMM_NOALLOC_SCRATCH_BYTES that the library holds on each GPU
+ * it runs on until the process ends; the call itself allocates nothing,
+ * creates no event and does not synchronise (queued on the plan's stream).
+ * The plan's constants must exist (gmm_plan_create allocates them).
+ * Workspace bytes for `count` fields (each of the parts rounded up to 256):
+ *   field rows        count N Nt c          (c = 16 for GMM_FP64, 8 otherwise)
+ *   pair rows         GMM_BF16X3 packed and rank-r routes: 512 count Nt;
+ *                     packed route: count Np Nt e; rank-r route: count max(Np, RQ) Nt e;
+ *                     general route: count KD Nt e
+ *                     (e = 8 for GMM_FP64, 4 otherwise; Np = N(N+1)/2; KD = 4 Np with
+ *                     Raman, 2 Np without, rounded up to 4)
+ *   rank-r route      count RQ Nt e         (RQ = rank rounded up to 16)
+ *   gain or coupling  count N^2 (C + 1) 16  (C = min(64, Nt/128))
+ * The 15-mode 2^14-sample BF16X3 plan takes about 13 MB per field, so up to 4
+ * fields a call.
+ * Returns GMM_ERR_UNSUPPORTED when count fields need more than the scratch
+ * (nothing is queued then).  Every call on one GPU shares that GPU's scratch
+ * and leaves its contents behind: calls that overlap on one GPU (different
+ * streams or host threads) race and must be ordered by the caller.
+ */
+#define GMM_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int gmm_nonlinear_noalloc(gmm_plan plan, const void* At, int count, void* out);
+
+/*
  * Batched propagations of one plan with continuous admission: the MPA of
  * Sec. III.D for up to `slots` independent propagations at once, each with its
  * own launch field, length and step (same plan: modes, tensors, grid,

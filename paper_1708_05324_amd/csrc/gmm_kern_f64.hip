@@ -137,6 +137,20 @@ hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double
   hipLaunchKernelGGL(k_gain_matrix, dim3(N, count), dim3(256), 0, s, part, C, SR, g, inv_Isat, dt, K, Mg, N, ctrl);
   return hipGetLastError();
 }
+// Zero fill of a device buffer (a kernel, so that a captured graph records no memset node).
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t* __restrict__ p, size_t words) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes % 4) return hipErrorInvalidValue;
+  const size_t words = bytes / 4;
+  if (words == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm_final_b(const BatchSlot* slots, int nslots, int nblocks, double tol, int fixed_iters,
                                int max_iter, hipStream_t s) {
   if (nslots < 1) return hipSuccess;

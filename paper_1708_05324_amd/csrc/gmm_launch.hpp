@@ -126,6 +126,8 @@ hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
 // Norm reduction and stop decision for each slot of a batched round (one block per slot).
 hipError_t launch_norm_final_b(const BatchSlot* slots, int nslots, int nblocks, double tol, int fixed_iters,
                                int max_iter, hipStream_t s);
+// Zero fill of `bytes` (a multiple of 4) at p, by a kernel.
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 // Mg_pl = g_p (delta_pl - inv_Isat sum_mn S^R_plmn Phi_mn) (g may be NULL) + K_pl (K may be NULL),
 // Phi = dt * sum of the chunk partials.
 hipError_t launch_gain_matrix(const cplx<double>* part, int C, const cplx<double>* SR, const double* g,

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -145,6 +146,7 @@ struct gmm_plan_s {
   gmm_params prm{};
   int N = 0, nt = 0, logn = 0, nb = 0, Np = 0, rt = 0, rpad = 0;
   hipStream_t stream = nullptr;
+  int device = -1;  // the GPU current when the plan was created (its buffers live there)
   double domega = 0, gamma_hat = 0;
   bool fp64 = true, raman = false, bf16 = false;
   size_t esz = 0;  // bytes per real of the field precision
@@ -297,7 +299,8 @@ int ensure_workspace(gmm_plan_s* P, int cap) {
 }
 
 // Device buffers one nonlinear evaluation works in: the plan's own workspace,
-// or a batch's buffers.
+// a batch's buffers, or slices of the static scratch of the no-allocation
+// entry point.
 struct EvalWs {
   void* work = nullptr;             // [cap][N][Nt] field rows
   void* Bp = nullptr;               // pair rows / Y' (layout of bp_bytes)
@@ -706,6 +709,54 @@ struct Runner {
     return rc;
   }
 
+  // The same evaluation with its buffers carved from `base` (scratch_bytes
+  // long): no allocation, no event, no synchronisation.
+  int nonlinear_noalloc(const void* At, int count, void* out, void* base, size_t scratch_bytes) {
+    const size_t need = noalloc_bytes(P, count);
+    if (need > scratch_bytes)
+      return fail(GMM_ERR_UNSUPPORTED, "gmm_nonlinear_noalloc: " + std::to_string(count) + " fields need " +
+                                           std::to_string(need) + " bytes of scratch, more than its " +
+                                           std::to_string(scratch_bytes));
+    EvalWs w;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+      void* q = (unsigned char*)base + off;
+      off += (bytes + 255) & ~(size_t)255;
+      return q;
+    };
+    w.cap = count;
+    w.work = carve((size_t)count * field_bytes(P));
+    w.Bp = carve(bp_bytes(P, count));
+    w.plane_words = (size_t)count * gmm::kBf16Kpad * P->nt / 2;
+    if (P->factored) w.Y = carve((size_t)count * P->rq * P->nt * P->esz);
+    if (P->gain_on || P->coupling_on) {
+      const size_t nn = (size_t)P->N * P->N;
+      w.gpart = (cplx<double>*)carve((size_t)count * gmm::gain_partials(P->nt) * nn * sizeof(cplx<double>));
+      w.Mg = (cplx<double>*)carve((size_t)count * nn * sizeof(cplx<double>));
+      w.gain_cap = count;
+    }
+    // rows the contraction reads with zero coefficients must hold zeros, as in the plan's own workspace
+    // (a fill kernel, not a memset node, so that the call can be captured in a graph)
+    if (P->bf16 || P->factored || P->dense) GMM_HIP(gmm::launch_fill_zero(w.Bp, bp_bytes(P, count), P->stream));
+    const bool prof_on = P->prof.on;  // no timing events here (creating one may allocate)
+    P->prof.on = false;
+    const int rc = eval((const cplx<T>*)At, P->N, count, 0, 0.0, (cplx<T>*)out, nullptr, 0, &w);
+    P->prof.on = prof_on;
+    return rc;
+  }
+
+  // Scratch bytes one no-allocation evaluation of `count` fields takes (each slice 256-byte aligned).
+  static size_t noalloc_bytes(const gmm_plan_s* P, int count) {
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t b = up((size_t)count * field_bytes(P)) + up(bp_bytes(P, count));
+    if (P->factored) b += up((size_t)count * P->rq * P->nt * P->esz);
+    if (P->gain_on || P->coupling_on) {
+      const size_t nn = (size_t)P->N * P->N;
+      b += up((size_t)count * gmm::gain_partials(P->nt) * nn * sizeof(cplx<double>)) +
+           up((size_t)count * nn * sizeof(cplx<double>));
+    }
+    return b;
+  }
 };
 
 template <typename T>
@@ -1229,6 +1280,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
     destroy(P);
     return code;
   };
+  if (hipGetDevice(&P->device) != hipSuccess) return bail(fail(GMM_ERR_HIP, "hipGetDevice failed"));
   // dispersion coefficients beta_n / n!
   std::vector<double> coef((size_t)N * P->nb);
   for (int q = 0; q < N; ++q) {
@@ -1612,6 +1664,37 @@ int batch_create(gmm_batch* out, gmm_plan_s* P, int slots, int M) {
   return GMM_OK;
 }
 
+// Static device scratch of gmm_nonlinear_noalloc: one copy per GPU, held
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// never the device memory: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (scratch_address below).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU `dev`, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMM_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    int cur = -1;
+    GMM_HIP(hipGetDevice(&cur));
+    if (cur != dev) GMM_HIP(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(GMM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1772,6 +1855,23 @@ int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out) {
   if (count < 1) return fail(GMM_ERR_ARG, "count must be >= 1");
   if (At == out) return fail(GMM_ERR_ARG, "out must not alias At");
   return plan->fp64 ? Runner<double>{plan}.nonlinear(At, count, out) : Runner<float>{plan}.nonlinear(At, count, out);
+}
+
+int gmm_nonlinear_noalloc(gmm_plan plan, const void* At, int count, void* out) {
+  if (!plan || !At || !out) return fail(GMM_ERR_ARG, "null argument");
+  if (count < 1) return fail(GMM_ERR_ARG, "count must be >= 1");
+  if (At == out) return fail(GMM_ERR_ARG, "out must not alias At");
+  try {
+    void* base = nullptr;
+    int rc = scratch_address(plan->device, &base);
+    if (rc) return rc;
+    rc = plan->fp64 ? Runner<double>{plan}.nonlinear_noalloc(At, count, out, base, kScratchBytes)
+                    : Runner<float>{plan}.nonlinear_noalloc(At, count, out, base, kScratchBytes);
+    if (rc == GMM_OK) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
 }
 
 int gmm_batch_create(gmm_batch* out, gmm_plan plan, int slots, int M) {

@@ -30,7 +30,7 @@ GMM_FP32 = 1
 GMM_BF16X3 = 2
 
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_plan_set_gain",
-           "gmm_plan_set_coupling", "gmm_plan_set_coupling_exact", "gmm_nonlinear",
+           "gmm_plan_set_coupling", "gmm_plan_set_coupling_exact", "gmm_nonlinear", "gmm_nonlinear_noalloc",
            "gmm_plan_destroy", "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable",
            "gmm_profile_read", "gmm_batch_create", "gmm_batch_submit", "gmm_batch_launch", "gmm_batch_wait",
            "gmm_batch_destroy", "gmm_batch_device_bytes")
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_plan_set_coupling_exact.restype = ci
     lib.gmm_nonlinear.argtypes = [vp, vp, ci, vp]
     lib.gmm_nonlinear.restype = ci
+    lib.gmm_nonlinear_noalloc.argtypes = [vp, vp, ci, vp]
+    lib.gmm_nonlinear_noalloc.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
     lib.gmm_plan_destroy.restype = ci
     lib.gmm_batch_create.argtypes = [ctypes.POINTER(vp), vp, ci, ci]
@@ -259,6 +261,20 @@ class Plan:
             out = torch.empty_like(At)
         _check(self.lib.gmm_nonlinear(self.handle, ctypes.c_void_p(At.data_ptr()), int(At.shape[0]),
                                       ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def nonlinear_noalloc(self, At, out):
+        """The same evaluation through gmm_nonlinear_noalloc: the library
+        allocates nothing (its workspace is the static device scratch); the
+        caller passes the output buffer."""
+        self._check_field(At)
+        self._check_field(out)
+        if At.dim() == 2:
+            At = At.unsqueeze(0)
+        if tuple(At.shape[1:]) != (self.n_modes, self.nt) or out.numel() != At.numel():
+            raise ValueError("At and out must be [count][N][Nt]")
+        _check(self.lib.gmm_nonlinear_noalloc(self.handle, ctypes.c_void_p(At.data_ptr()), int(At.shape[0]),
+                                              ctypes.c_void_p(out.data_ptr())))
         return out
 
     def profile(self, kinds=True):
