@@ -286,6 +286,73 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
     }
 
 
+def bench_batch(length_scale: float) -> dict:
+    """The batched workload: one FP32 plan per shape class (modes, samples), its
+    contraction launch autotuned for the batch's rows, each on its own stream;
+    every propagation of a class goes into one batch of that class, and the
+    rounds of all classes are queued together.  Baseline: the same plans
+    propagating the same problems one after another.  The outputs of the two
+    are compared bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1708_05324_amd import gmmpa, synth
+    probs = synth.batch_problems(length_scale=length_scale)
+    classes = sorted({p.extra["class"] for p in probs})
+    plans, batches, tune = {}, {}, {}
+    for cl in classes:
+        w = next(p for p in probs if p.extra["class"] == cl)
+        n_in = sum(1 for p in probs if p.extra["class"] == cl)
+        plan = gmmpa.plan_from_workload(w, precision="fp32", tol=TOL["fp32"], max_iter=30,
+                                        stream=torch.cuda.Stream())
+        choice, us = plan.autotune(n_in * (w.M + 1))
+        tune[f"{cl[0]}x{cl[1]}"] = {"chosen": choice, "us_per_launch": [round(x, 2) for x in us],
+                                    "route": "rank-r" if plan.rank() else "packed"}
+        plans[cl] = plan
+        batches[cl] = gmmpa.Batch(plan, slots=n_in, M=w.M)
+    order = {cl: i for i, cl in enumerate(classes)}
+    inputs = [torch.from_numpy(p.A0).to(device="cuda", dtype=torch.complex64) for p in probs]
+    torch.cuda.synchronize()
+    small = sum(int(round(p.L / p.dz)) for p in probs)
+    # warm-up: one short propagation per class through its batch and alone
+    for cl in classes:
+        p = next(q for q in probs if q.extra["class"] == cl)
+        A = torch.from_numpy(p.A0).to(device="cuda", dtype=torch.complex64)
+        torch.cuda.synchronize()
+        gmmpa.run_batches([batches[cl]], [(0, A, 2 * p.M * p.dz, p.dz, -1)])
+        plans[cl].propagate(A, 2 * p.M * p.dz, p.dz, p.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = gmmpa.run_batches([batches[cl] for cl in classes],
+                            [(order[p.extra["class"]], inputs[i], p.L, p.dz, i) for i, p in enumerate(probs)])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    seq = []
+    t0 = time.perf_counter()
+    for i, p in enumerate(probs):
+        seq.append(plans[p.extra["class"]].propagate(inputs[i], p.L, p.dz, p.M))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    equal = all(np.array_equal(res[i][2].cpu().numpy(), seq[i].field.cpu().numpy()) and
+                res[i][1]["iterations"] == seq[i].stats["iterations"] for i in range(len(probs)))
+    evals = sum(r.stats["evaluations"] for r in seq)
+    out = {"metric": "batched MPA propagations: small steps/s over 64 problems of uneven modes and samples",
+           "unit": "small steps/s", "value": round(small / t_batch, 1), "dtype": "f32",
+           "config": {"workload": "grin_batch64", "problems": len(probs), "classes": len(classes),
+                      "modes": [3, 6, 10, 15], "nt": [4096, 8192, 16384], "lengths_m": [0.1 * length_scale,
+                                                                                       1.0 * length_scale],
+                      "energy_nJ": [1, 200], "chirp": [-5, 5], "M": 10, "tol": TOL["fp32"]},
+           "small_steps": small, "evaluations": evals, "seconds_batched": round(t_batch, 3),
+           "sequential": {"small_steps_per_s": round(small / t_seq, 1), "seconds": round(t_seq, 3)},
+           "speedup_vs_sequential": round(t_seq / t_batch, 3), "problems_per_s": round(len(probs) / t_batch, 2),
+           "bitwise_equal_to_sequential": bool(equal), "autotune": tune,
+           "batch_device_bytes": sum(b.device_bytes() for b in batches.values())}
+    for b in batches.values():
+        b.close()
+    for pl in plans.values():
+        pl.close()
+    return out
+
+
 def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
     """The FP64 oracle on the host: large steps (M small steps each) of the same
     workload from its launch field, until at least min_seconds of work.  The
@@ -344,6 +411,12 @@ def main():
                     help="only time the metric workload with the terms of Sec. III.F on (saturating gain, "
                          "g = 2/m per mode, I_sat = 2 S_0000 E_pulse; linear coupling, a random symmetric Q of "
                          "20/m entries) and print its own JSON line")
+    ap.add_argument("--batch", action="store_true",
+                    help="only run the batched workload (64 GRIN propagations of 3-15 modes and 2^12-2^14 samples, "
+                         "FP32, autotuned contraction): batched rounds against the same propagations one after "
+                         "another, and print its own JSON line")
+    ap.add_argument("--length-scale", type=float, default=0.05,
+                    help="batched workload: fibre lengths are uniform in [0.1, 1] m times this factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -457,6 +530,9 @@ def main():
         if r["breakdown"]:
             out["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in r["breakdown"].items()}
         print(json.dumps(out), flush=True)
+        return
+    if args.batch:
+        print(json.dumps(bench_batch(args.length_scale)), flush=True)
         return
     if args.copy_probe:
         n = 256 * 2 ** 20 // 4

@@ -235,6 +235,31 @@ int gmm_nonlinear(gmm_plan plan, const void* At, int count, void* out);
 int gmm_nonlinear_noalloc(gmm_plan plan, const void* At, int count, void* out);
 
 /*
+ * gmm_plan_autotune - choose the launch of the contraction (a4 + a5 of the
+ * iteration, the MFMA product and the mode projection) for this plan by
+ * timing the candidates on the plan's own buffers, `count` sub-step rows per
+ * launch (M + 1 for gmm_propagate, slots (M + 1) for a batch); the fastest is
+ * kept for every later call on the plan (propagate, batches, gmm_nonlinear).
+ *   FP32 rank-r route: column-owner kernel at 1 or 2 blocks per CU, or the
+ *   row-register kernel at 1 to 4 blocks per CU (these two kernels sum in a
+ *   different order, so their results differ by rounding);
+ *   FP32 packed route: the row-register kernel at 1 to 4 blocks per CU;
+ *   BF16X3 rank-r route: the column-owner kernel at 1 or 2 blocks per CU.
+ * Other routes: GMM_ERR_UNSUPPORTED.  Allocates the plan's workspace for
+ * `count` rows, overwrites it and synchronises the plan's stream.
+ *   n_candidates : receives the number of candidates (may be NULL).
+ *   us           : receives the mean microseconds per launch of candidate i,
+ *                  for i < max_candidates (may be NULL).
+ * Returns the index of the chosen candidate (>= 0) or an error.
+ */
+int gmm_plan_autotune(gmm_plan plan, int count, int* n_candidates, double* us, int max_candidates);
+
+/* Use contraction candidate `candidate` (numbered as by gmm_plan_autotune,
+ * e.g. a tuning result kept from an earlier run) for every later call on the
+ * plan.  GMM_ERR_ARG if the plan's route has no such candidate. */
+int gmm_plan_set_contraction(gmm_plan plan, int candidate);
+
+/*
  * Batched propagations of one plan with continuous admission: the MPA of
  * Sec. III.D for up to `slots` independent propagations at once, each with its
  * own launch field, length and step (same plan: modes, tensors, grid,

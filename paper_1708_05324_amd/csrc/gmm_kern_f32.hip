@@ -77,12 +77,13 @@ static int contract_cols_blocks() {
 
 hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
                                 cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
-                                hipStream_t s) {
+                                hipStream_t s, int blocks_per_cu) {
   const int ntiles = count * (Nt / 64);
 #define GMM_COL_CASE(RP, BF)                                                                                  \
   if (rpad == RP && bf16 == BF) {                                                                             \
-    const int cap = contract_cols_blocks<RP, BF>();                                                          \
+    int cap = contract_cols_blocks<RP, BF>();                                                                \
     if (cap < 1) return hipErrorInvalidConfiguration;                                                        \
+    if (blocks_per_cu > 0) cap = std::min(cap, blocks_per_cu * device_cus());                                \
     const int nb = std::min((ntiles + 3) / 4, cap);                                                          \
     hipLaunchKernelGGL((k_contract_cols<RP, BF>), dim3(nb), dim3(256), (ColShape<RP, BF>::lds_bytes()), s, Ua, \
                        Ub, Ya, Yb, A_NL, N, kv, Nt, ntiles, ctrl);                                           \

@@ -36,8 +36,9 @@ struct Launch {
   static hipError_t pairs(int logn, bool raman, const cplx<T>* A, T* Bp, const int2* pairs, int N, int Np,
                           int count, const cplx<T>* Gs, const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   // kpad = 0: packed matrix with K = Rpad (kv = Np rows per sub-step); kpad = 64: rank factor U (kv = RQ).
+  // blocks_per_cu > 0: at most that many blocks per CU for the persistent variants (0: as many as fit)
   static hipError_t contract(int rt, int kpad, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N,
-                             int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
+                             int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s, int blocks_per_cu = 0);
   static hipError_t project(int rq, int kp, const T* VT, const cplx<T>* A, T* Y, const int2* pairs, int N, int Np,
                             int Nt, int count, const Ctrl* ctrl, hipStream_t s);
   static hipError_t conv(int logn, const T* Y, T* Yout, int R, int RQ, int count, const cplx<T>* Gs,
@@ -93,7 +94,7 @@ hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* S
 // 2-row words, kv valid rows) or FP32 (Ua = U^T [64][Rpad], Ya = Y' [count][kv][Nt]).
 hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
                                 cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
-                                hipStream_t s);
+                                hipStream_t s, int blocks_per_cu = 0);
 // Column-owner projection Y = V B of the rank-r route (complex64 fields, RQ <= 64,
 // KPAD 64 or 128): BF16 split (Va/Vb = V hi/lo [RQ][KPAD] bf16) or FP32 (Va = V^T [KPAD][RQ]).
 hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, const void* Vb, const cplx<float>* A,

@@ -169,11 +169,13 @@ inline int device_cus() {
 
 template <typename T>
 hipError_t Launch<T>::contract(int rt, int kpad, const T* ST, const T* Bp, cplx<T>* A_NL, const int* pidx, int N,
-                               int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s) {
+                               int kv, int Nt, int count, const Ctrl* ctrl, hipStream_t s, int blocks_per_cu) {
   const int ntiles = count * (Nt / 64);
 #define GMM_RT_REG(R, KP)                                                                                   \
   if (rt == R && (kpad == KP || (kpad == 0 && KP == 64 * R))) {                                              \
-    const int nb = std::min(ntiles, contract_reg_blocks<T, R, KP>());                                        \
+    int cap = contract_reg_blocks<T, R, KP>();                                                               \
+    if (blocks_per_cu > 0) cap = std::min(cap, blocks_per_cu * device_cus());                                \
+    const int nb = std::min(ntiles, cap);                                                                    \
     hipLaunchKernelGGL((k_contract_reg<T, R, KP>), dim3(nb), dim3(256), (contract_reg_lds<R, T>()), s, ST, Bp, \
                        A_NL, pidx, N, kv, Nt, ntiles, ctrl);                                                 \
     return hipGetLastError();                                                                                \

@@ -160,6 +160,9 @@ struct gmm_plan_s {
   // rank-r route (Raman on, low-rank packed matrix): S^ = U V
   bool factored = false;
   int rank = 0, rq = 0, kp = 0;  // r, r rounded up to 16, Np rounded up to 64
+  // contraction launch chosen by gmm_plan_autotune: kernel (rank-r FP32 route: 0 column-owner, 1 row-register)
+  // and blocks per CU of the persistent grid (0: as many as fit)
+  int tune_kernel = 0, tune_bpc = 0;
   void* VT = nullptr;      // [kp][rq] V transposed, field precision
   void* UT = nullptr;      // [64][rpad] U transposed (contraction operand, K = 64)
   void* Uhi = nullptr;     // [rpad][64] bf16 split of U, K contiguous (BF16X3)
@@ -324,6 +327,27 @@ EvalWs plan_ws(const gmm_plan_s* P) {
   return w;
 }
 
+// Launch candidates of the contraction that gmm_plan_autotune times, in its
+// numbering: kernel (rank-r FP32 route: 0 column-owner, 1 row-register) and
+// blocks per CU of the persistent grid.
+struct ContractCand {
+  int kernel, bpc;
+};
+std::vector<ContractCand> contraction_candidates(const gmm_plan_s* P) {
+  std::vector<ContractCand> c;
+  if (P->fp64 || P->dense) return c;
+  if (P->factored && !P->bf16) {
+    for (int b : {1, 2}) c.push_back({0, b});
+    if (P->rt <= 2)
+      for (int b : {1, 2, 3, 4}) c.push_back({1, b});
+  } else if (P->factored) {
+    for (int b : {1, 2}) c.push_back({0, b});
+  } else if (!P->bf16 && P->rt <= 2) {
+    for (int b : {1, 2, 3, 4}) c.push_back({0, b});
+  }
+  return c;
+}
+
 // ---------------------------------------------------------------------------
 // Typed sequencing of one nonlinear evaluation and one iteration.
 template <typename T>
@@ -390,7 +414,8 @@ struct Runner {
                                                                 (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
           if (doB)
             GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
-                                                                     P->N, R, P->nt, count, ctrl, P->stream));
+                                                                     P->N, R, P->nt, count, ctrl, P->stream,
+                                                                     P->tune_bpc));
         }
       }
       if (!P->bf16) {
@@ -403,9 +428,14 @@ struct Runner {
           GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<T>::conv(P->logn, Y, (T*)ws.Bp, R, P->rq, count,
                                                         (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
         if constexpr (std::is_same<T, float>::value) {
-          if (doB)
+          if (doB && P->tune_kernel == 1)
+            GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)ws.Bp, W,
+                                                                 P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream,
+                                                                 P->tune_bpc));
+          else if (doB)
             GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, ws.Bp, nullptr,
-                                                                     W, P->N, P->rq, P->nt, count, ctrl, P->stream));
+                                                                     W, P->N, P->rq, P->nt, count, ctrl, P->stream,
+                                                                     P->tune_bpc));
         } else if (doB) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)ws.Bp, W,
                                                                P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream));
@@ -438,7 +468,8 @@ struct Runner {
                                                      (const cplx<T>*)P->Hs, tw(), ctrl, P->stream));
       if (doB)
         GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 0, (const T*)P->ST, (const T*)ws.Bp, W, P->pidx,
-                                                           P->N, P->Np, P->nt, count, ctrl, P->stream));
+                                                           P->N, P->Np, P->nt, count, ctrl, P->stream,
+                                                           P->tune_bpc));
     }
     return GMM_OK;
   }
@@ -707,6 +738,56 @@ struct Runner {
       P->prof.collect();
     }
     return rc;
+  }
+
+  // Time the candidate launches of the contraction on the plan's own buffers
+  // for `count` rows and keep the fastest (see gmm_plan_autotune).
+  int autotune(int count, int* n_cand, double* us, int max_cand) {
+    const std::vector<ContractCand> cands = contraction_candidates(P);
+    if (cands.empty())
+      return fail(GMM_ERR_UNSUPPORTED, "the autotuner covers the FP32 packed and rank-r routes and the BF16X3 "
+                                       "rank-r route");
+    int rc = ensure_workspace(P, count);
+    if (rc) return rc;
+    GMM_HIP(hipMemsetAsync(P->work, 0, (size_t)count * field_bytes(P), P->stream));
+    GMM_HIP(hipMemsetAsync(P->Bp, 0, bp_bytes(P, P->cap), P->stream));
+    hipEvent_t e0, e1;
+    GMM_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(GMM_ERR_HIP, "hipEventCreate failed");
+    }
+    const bool prof_on = P->prof.on;
+    P->prof.on = false;
+    const EvalWs ws = plan_ws(P);
+    int best = -1;
+    double best_us = 0.0;
+    for (size_t c = 0; c < cands.size() && rc == GMM_OK; ++c) {
+      P->tune_kernel = cands[c].kernel;
+      P->tune_bpc = cands[c].bpc;
+      constexpr int kWarm = 2, kRuns = 5;
+      for (int i = 0; i < kWarm && rc == GMM_OK; ++i) rc = mid(count, ws, nullptr, false, true);
+      if (rc == GMM_OK && hipEventRecord(e0, P->stream) != hipSuccess) rc = fail(GMM_ERR_HIP, "hipEventRecord");
+      for (int i = 0; i < kRuns && rc == GMM_OK; ++i) rc = mid(count, ws, nullptr, false, true);
+      if (rc == GMM_OK && hipEventRecord(e1, P->stream) != hipSuccess) rc = fail(GMM_ERR_HIP, "hipEventRecord");
+      float ms = 0.f;
+      if (rc == GMM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(GMM_ERR_HIP, "event timing failed");
+      const double t = 1e3 * ms / kRuns;
+      if ((int)c < max_cand && us) us[c] = t;
+      if (rc == GMM_OK && (best < 0 || t < best_us)) {
+        best = (int)c;
+        best_us = t;
+      }
+    }
+    P->prof.on = prof_on;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    P->tune_kernel = cands[best].kernel;
+    P->tune_bpc = cands[best].bpc;
+    if (n_cand) *n_cand = (int)cands.size();
+    return best;
   }
 
   // The same evaluation with its buffers carved from `base` (scratch_bytes
@@ -1872,6 +1953,28 @@ int gmm_nonlinear_noalloc(gmm_plan plan, const void* At, int count, void* out) {
   } catch (...) {
     return fail(GMM_ERR_NOMEM, "host allocation failed");
   }
+}
+
+int gmm_plan_autotune(gmm_plan plan, int count, int* n_candidates, double* us, int max_candidates) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  if (count < 1 || count > 4096) return fail(GMM_ERR_ARG, "count must be 1..4096");
+  try {
+    const int rc = plan->fp64 ? Runner<double>{plan}.autotune(count, n_candidates, us, max_candidates)
+                              : Runner<float>{plan}.autotune(count, n_candidates, us, max_candidates);
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (...) {
+    return fail(GMM_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+int gmm_plan_set_contraction(gmm_plan plan, int candidate) {
+  if (!plan) return fail(GMM_ERR_ARG, "null plan");
+  const std::vector<ContractCand> c = contraction_candidates(plan);
+  if (candidate < 0 || candidate >= (int)c.size()) return fail(GMM_ERR_ARG, "no such contraction candidate");
+  plan->tune_kernel = c[candidate].kernel;
+  plan->tune_bpc = c[candidate].bpc;
+  return GMM_OK;
 }
 
 int gmm_batch_create(gmm_batch* out, gmm_plan plan, int slots, int M) {

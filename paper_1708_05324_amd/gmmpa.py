@@ -32,7 +32,7 @@ GMM_BF16X3 = 2
 EXPORTS = ("gmm_plan_create", "gmm_propagate", "gmm_propagate_rk4ip", "gmm_plan_set_gain",
            "gmm_plan_set_coupling", "gmm_plan_set_coupling_exact", "gmm_nonlinear", "gmm_nonlinear_noalloc",
            "gmm_plan_destroy", "gmm_last_error", "gmm_plan_device_bytes", "gmm_plan_rank", "gmm_profile_enable",
-           "gmm_profile_read", "gmm_batch_create", "gmm_batch_submit", "gmm_batch_launch", "gmm_batch_wait",
+           "gmm_profile_read", "gmm_plan_autotune", "gmm_plan_set_contraction", "gmm_batch_create", "gmm_batch_submit", "gmm_batch_launch", "gmm_batch_wait",
            "gmm_batch_destroy", "gmm_batch_device_bytes")
 PROFILE_KINDS = ("phase_to_time", "pairs_raman", "contract", "spectral_out", "trapz", "norm", "close", "project",
                  "gain")
@@ -88,6 +88,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gmm_nonlinear_noalloc.restype = ci
     lib.gmm_plan_destroy.argtypes = [vp]
     lib.gmm_plan_destroy.restype = ci
+    lib.gmm_plan_autotune.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(dbl), ci]
+    lib.gmm_plan_autotune.restype = ci
+    lib.gmm_plan_set_contraction.argtypes = [vp, ci]
+    lib.gmm_plan_set_contraction.restype = ci
     lib.gmm_batch_create.argtypes = [ctypes.POINTER(vp), vp, ci, ci]
     lib.gmm_batch_create.restype = ci
     lib.gmm_batch_submit.argtypes = [vp, vp, dbl, dbl, vp, ctypes.c_longlong]
@@ -276,6 +280,20 @@ class Plan:
         _check(self.lib.gmm_nonlinear_noalloc(self.handle, ctypes.c_void_p(At.data_ptr()), int(At.shape[0]),
                                               ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def autotune(self, count: int):
+        """Time the contraction launch candidates for `count` rows per launch and
+        keep the fastest: returns (chosen index, [microseconds per launch])."""
+        n = ctypes.c_int()
+        us = (ctypes.c_double * 16)()
+        rc = self.lib.gmm_plan_autotune(self.handle, int(count), ctypes.byref(n), us, 16)
+        if rc < 0:
+            _check(rc)
+        return rc, [us[i] for i in range(n.value)]
+
+    def set_contraction(self, candidate: int):
+        """Use contraction launch candidate `candidate` (numbered as by autotune)."""
+        _check(self.lib.gmm_plan_set_contraction(self.handle, int(candidate)))
 
     def profile(self, kinds=True):
         """Start (and zero) per-kernel HIP-event timing inside the library for the

@@ -271,6 +271,43 @@ def fig3_workload() -> Workload:
     return w
 
 
+def batch_problems(seed: int = 4, count: int = 64, length_scale: float = 1.0) -> list[Workload]:
+    """The batched workload: `count` independent GRIN propagations, all drawn
+    from numpy.random.default_rng(170805324 + seed) in this order per problem:
+    Hermite-Gauss groups g in {2, 3, 4, 5} (3, 6, 10, 15 modes), log2 Nt in
+    {12, 13, 14} (dt = 2.441 fs: windows of 10, 20, 40 ps), length uniform in
+    [0.1, 1] m (times length_scale), energy log-uniform in [1, 200] nJ, linear
+    chirp C uniform in [-5, 5] (a Gaussian of 200 fs FWHM with the phase
+    exp(-i C t^2 / 2 T0^2), so its spectrum is sqrt(1 + C^2) times wider than
+    transform-limited), then the mode phases.
+    Equal energy over the modes, Kerr + Raman (fR = 0.18) + shock, M = 10, dz by
+    the z_NL / z_IM rule."""
+    rng = np.random.default_rng(SEED_BASE + seed)
+    out = []
+    for i in range(count):
+        groups = int(rng.choice([2, 3, 4, 5]))
+        logn = int(rng.choice([12, 13, 14]))
+        L = float(rng.uniform(0.1, 1.0)) * length_scale
+        E = float(np.exp(rng.uniform(np.log(1e-9), np.log(200e-9))))
+        C = float(rng.uniform(-5.0, 5.0))
+        fib = GrinFiber()
+        modes = hg_modes(groups)
+        N = len(modes)
+        nt = 2 ** logn
+        t = time_grid(nt, DT_FINE)
+        ph = rng.uniform(0.0, 2.0 * math.pi, N)
+        c = np.sqrt(np.full(N, 1.0 / N)) * np.exp(1j * ph)
+        shape = gaussian_pulse(t, 200e-15, 1.0, C)
+        P0 = E / (float(np.sum(np.abs(shape) ** 2)) * DT_FINE)   # peak power for energy E on the grid
+        A0 = (math.sqrt(P0) * c[:, None] * shape[None, :]).astype(np.complex128)
+        w = grin_workload(seed, groups, nt, DT_FINE, "gaussian", 200e-15, peak_power=P0, fR=0.18,
+                          self_steepening=1, M=10, L=L, name=f"batch{i}_g{groups}_nt{nt}")
+        w.A0 = A0
+        w.extra.update({"energy": E, "chirp": C, "class": (N, nt)})
+        out.append(w)
+    return out
+
+
 def random_fields(seed: int, n_modes: int, nt: int, scale: float = 1.0) -> np.ndarray:
     """Smooth-ish random complex fields [N][nt] for operator-level parity checks."""
     rng = np.random.default_rng(SEED_BASE + 1000 + seed)

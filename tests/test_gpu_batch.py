@@ -52,13 +52,17 @@ KEYS = ("large_steps", "small_steps", "iterations", "evaluations", "max_iters_se
         "last_eps", "dz_used", "energy_in", "energy_out", "photons_in", "photons_out")
 
 
-@pytest.mark.parametrize("prec,fixed", [("fp64", 0), ("fp32", 0), ("bf16x3", 0), ("fp32", 3)])
-def test_batch_equals_solo_bitwise(torch_gpu, prec, fixed):
+@pytest.mark.parametrize("prec,fixed,tuned", [("fp64", 0, False), ("fp32", 0, False), ("bf16x3", 0, False),
+                                              ("fp32", 3, False), ("fp32", 0, True)])
+def test_batch_equals_solo_bitwise(torch_gpu, prec, fixed, tuned):
     from paper_1708_05324_amd import gmmpa
     torch = torch_gpu
-    w = synth.config2()                                 # 6 modes, 2^13 samples, rank-r route, Raman + shock
+    w = synth.config2()                                 # 6 modes, 2^13 samples, packed route, Raman + shock
     tol = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}[prec]
     plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30, fixed_iters=fixed)
+    if tuned:                                           # the tuned launch is the plan's: batch and solo share it
+        choice, us = plan.autotune(3 * (w.M + 1))
+        print(f"[autotune] chose {choice} of {[round(x, 1) for x in us]} us", flush=True)
     jobs = problems(w, 7, 0)
     batch = gmmpa.Batch(plan, slots=3, M=w.M)           # 7 propagations through 3 slots: admission mid-flight
     inputs = [(0, to_dev(torch, A0, prec), L, dz, i) for i, (A0, L, dz) in enumerate(jobs)]
@@ -148,3 +152,34 @@ def test_batch_slot_errors_and_divergence(torch_gpu):
         gmmpa.Batch(plan, slots=1, M=w.M)
     assert e.value.code == gmmpa.GMM_ERR_UNSUPPORTED
     plan.close()
+
+
+def test_autotune_candidates_match_the_oracle(torch_gpu):
+    """Every contraction launch the autotuner can choose, on the FP32 rank-r
+    route (15 modes) and the FP32 packed route (6 modes), evaluates the
+    oracle's nonlinear operator; the autotuner times all of them and keeps one."""
+    from oracle import gmmnlse as O
+    from paper_1708_05324_amd import gmmpa
+    torch = torch_gpu
+    for groups, rank in ((5, 45), (3, 0)):
+        w = synth.grin_workload(12, groups, 2 ** 11, 10e-15, "sech", 200e-15, peak_power=2e5, fR=0.18,
+                                self_steepening=1, M=5, L=0.01)
+        plan = gmmpa.plan_from_workload(w, precision="fp32")
+        assert plan.rank() == rank
+        ops = O._Ops(O.model_from_workload(w), w.nt)
+        fields = [w.A0 * np.exp(0.4j * c) + 0.2 * synth.random_fields(c, w.n_modes, w.nt, scale=300.0)
+                  for c in range(3)]
+        At = np.stack([O.to_spectrum(a) for a in fields])
+        ref = np.stack([ops.N(a) for a in At])
+        dev = torch.from_numpy(At).to(device="cuda", dtype=torch.complex64)
+        choice, us = plan.autotune(3)
+        assert 0 <= choice < len(us) and all(x > 0 for x in us)
+        for c in range(len(us)):
+            plan.set_contraction(c)
+            got = plan.nonlinear(dev).cpu().numpy()
+            err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+            print(f"[{w.n_modes} modes candidate {c}] {us[c]:.1f} us, operator error {err:.3e}", flush=True)
+            assert err < 2e-5
+        with pytest.raises(gmmpa.GmmError):
+            plan.set_contraction(len(us))
+        plan.close()
