@@ -353,6 +353,32 @@ def bench_batch(length_scale: float) -> dict:
     return out
 
 
+def bench_serve(args) -> dict:
+    """Serve the seeded Poisson stream at the offered rate, then at 0.7 times
+    the capacity measured in that run (served requests per second; a second
+    stream of the same draws with the arrival times stretched)."""
+    from paper_1708_05324_amd import serve, synth
+    reqs = synth.request_stream(count=args.requests, rate=args.rate, length_scale=args.serve_length_scale)
+    warm = synth.request_stream(seed=6, count=12, rate=1e4, length_scale=0.001)
+    srv = serve.Server(precision="bf16x3")
+    srv.prepare(reqs)
+    srv.run(warm, realtime=False)                        # code loading, first batches of several classes
+    _, first = srv.run(reqs, realtime=True)
+    capacity = first["served_requests_per_s"]
+    slow = [synth.Request(r.idx, r.arrival * args.rate / (0.7 * capacity), r.groups, r.nt, r.L, r.A0, r.energy,
+                          r.chirp) for r in reqs]
+    _, second = srv.run(slow, realtime=True)
+    srv.close()
+    return {"metric": "served GRIN propagations: p50/p99 latency and throughput under a Poisson stream",
+            "unit": "ms", "value": first["latency_ms_p50"], "dtype": "bf16x3+f32 (FP64 norm)",
+            "config": {"workload": "grin_serve", "requests": args.requests, "rate_per_s": args.rate,
+                       "groups": [1, 5], "modes_max": 15, "nt": [4096, 32768],
+                       "lengths_m": [0.1 * args.serve_length_scale, 2.0 * args.serve_length_scale],
+                       "energy_nJ": [1, 200], "chirp": [-5, 5], "M": 10, "slots_per_batch": srv.slots,
+                       "budget_GiB": srv.budget_bytes / 2 ** 30},
+            "at_offered_rate": first, "at_0.7x_capacity": dict(second, offered_rate_per_s=round(0.7 * capacity, 3))}
+
+
 def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
     """The FP64 oracle on the host: large steps (M small steps each) of the same
     workload from its launch field, until at least min_seconds of work.  The
@@ -417,6 +443,14 @@ def main():
                          "another, and print its own JSON line")
     ap.add_argument("--length-scale", type=float, default=0.05,
                     help="batched workload: fibre lengths are uniform in [0.1, 1] m times this factor")
+    ap.add_argument("--serve", action="store_true",
+                    help="only run the serving workload (seeded Poisson stream of GRIN requests of 1-15 modes and "
+                         "2^12-2^15 samples, BF16X3 with the FP64 norm) at the offered rate and at 0.7x the "
+                         "measured capacity, and print its own JSON line")
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests per stream")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: offered requests per second")
+    ap.add_argument("--serve-length-scale", type=float, default=0.01,
+                    help="serving: lengths are uniform in [0.1, 2] m times this factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -530,6 +564,9 @@ def main():
         if r["breakdown"]:
             out["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in r["breakdown"].items()}
         print(json.dumps(out), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(bench_serve(args)), flush=True)
         return
     if args.batch:
         print(json.dumps(bench_batch(args.length_scale)), flush=True)

@@ -308,6 +308,48 @@ def batch_problems(seed: int = 4, count: int = 64, length_scale: float = 1.0) ->
     return out
 
 
+@dataclass
+class Request:
+    """One served propagation request."""
+    idx: int
+    arrival: float          # seconds after the start of the stream
+    groups: int             # Hermite-Gauss groups (N = groups (groups + 1) / 2 modes)
+    nt: int
+    L: float
+    A0: np.ndarray          # [N][nt] complex128 launch field
+    energy: float
+    chirp: float
+
+
+def request_stream(seed: int = 5, count: int = 200, rate: float = 200.0, max_groups: int = 5,
+                   length_scale: float = 0.01) -> list[Request]:
+    """A seeded Poisson request stream of GRIN propagations: exponential gaps of
+    mean 1/rate, then per request (draw order) Hermite-Gauss groups uniform in
+    1..max_groups, log2 Nt uniform in 12..15 (dt = 2.441 fs), length uniform in
+    [0.1, 2] m times length_scale, energy log-uniform in [1, 200] nJ, chirp
+    uniform in [-5, 5] (200 fs FWHM Gaussian), mode phases; equal energy over
+    the modes.  Kerr + Raman + shock and the step rule are the plan's and the
+    server's (see serve.py)."""
+    rng = np.random.default_rng(SEED_BASE + seed)
+    gaps = rng.exponential(1.0 / rate, count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(count):
+        groups = int(rng.integers(1, max_groups + 1))
+        nt = 2 ** int(rng.integers(12, 16))
+        L = float(rng.uniform(0.1, 2.0)) * length_scale
+        E = float(np.exp(rng.uniform(np.log(1e-9), np.log(200e-9))))
+        C = float(rng.uniform(-5.0, 5.0))
+        N = n_modes_for_groups(groups)
+        ph = rng.uniform(0.0, 2.0 * math.pi, N)
+        c = np.sqrt(np.full(N, 1.0 / N)) * np.exp(1j * ph)
+        shape = gaussian_pulse(time_grid(nt, DT_FINE), 200e-15, 1.0, C)
+        P0 = E / (float(np.sum(np.abs(shape) ** 2)) * DT_FINE)
+        A0 = (math.sqrt(P0) * c[:, None] * shape[None, :]).astype(np.complex128)
+        out.append(Request(i, float(arrivals[i]), groups, nt, L, A0, E, C))
+    return out
+
+
 def random_fields(seed: int, n_modes: int, nt: int, scale: float = 1.0) -> np.ndarray:
     """Smooth-ish random complex fields [N][nt] for operator-level parity checks."""
     rng = np.random.default_rng(SEED_BASE + 1000 + seed)
