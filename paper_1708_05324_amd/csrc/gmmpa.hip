@@ -209,6 +209,7 @@ struct gmm_plan_s {
   double* partials = nullptr;
   Ctrl* ctrl = nullptr;
   Ctrl* h_ctrl = nullptr;         // pinned
+  hipEvent_t ev = nullptr;        // marks the stop-flag copy the host waits for
   double* h_partials = nullptr;   // pinned
   long long const_bytes = 0, ws_bytes = 0;
   GmmProfiler prof;
@@ -634,16 +635,13 @@ struct Runner {
         n_enq = 1;
         for (;;) {
           GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
-          hipEvent_t ev;
-          GMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-          GMM_HIP(hipEventRecord(ev, P->stream));
+          GMM_HIP(hipEventRecord(P->ev, P->stream));
           const bool more = n_enq < P->prm.max_iter;
           if (more) {
             P->prof.cur_iter = n_enq + 1;
-            if ((rc = iteration(m, dz, false, 1))) { (void)hipEventDestroy(ev); return rc; }
+            if ((rc = iteration(m, dz, false, 1))) return rc;
           }
-          GMM_HIP(hipEventSynchronize(ev));
-          GMM_HIP(hipEventDestroy(ev));
+          GMM_HIP(hipEventSynchronize(P->ev));
           if (P->h_ctrl->done || !more) break;
           if ((rc = iteration(m, dz, false, 2))) return rc;
           ++n_enq;
@@ -1257,6 +1255,7 @@ void destroy(gmm_plan_s* P) {
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
+  if (P->ev) (void)hipEventDestroy(P->ev);
   if (P->h_partials) (void)hipHostFree(P->h_partials);
   delete P;
 }
@@ -1422,6 +1421,8 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
         (rc = fp64 ? build_overlap_save<double>(P, hR, blend) : build_overlap_save<float>(P, hR, blend)))
       return bail(rc);
   }
+  if (hipEventCreateWithFlags(&P->ev, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "hipEventCreate failed"));
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
   if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&P->h_partials, 2 * sizeof(double) * gmm::trapz_blocks((long)N * nt),

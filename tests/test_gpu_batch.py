@@ -83,6 +83,43 @@ def test_batch_equals_solo_bitwise(torch_gpu, prec, fixed, tuned):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_equals_solo_bitwise_rank_route(torch_gpu, prec):
+    """The 15-mode rank-45 route at 2^13 samples (Y = V B, overlap-save
+    convolution of the 45 rows, column-owner contraction): batch and single
+    propagation agree bit for bit, and the single propagation agrees with the
+    oracle over one large step."""
+    from oracle import gmmnlse as O
+    from paper_1708_05324_amd import gmmpa
+    torch = torch_gpu
+    w = synth.grin_workload(3, 5, 2 ** 13, synth.DT_FINE, "gaussian", 200e-15, energy=100e-9, fR=0.18,
+                            self_steepening=1, M=10, L=1.0)
+    tol = {"fp32": 1e-6, "bf16x3": 3e-5}[prec]
+    plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
+    assert plan.rank() == 45
+    ref = O.mpa_propagate(w.A0, O.model_from_workload(w), w.M * w.dz, w.dz, w.M, fixed_iters=3)
+    fixed = gmmpa.plan_from_workload(w, precision=prec, fixed_iters=3)
+    got = fixed.propagate(to_dev(torch, w.A0, prec), w.M * w.dz, w.dz, w.M).field.cpu().numpy()
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"[{prec} rank-45 2^13] one large step vs oracle {err:.3e}", flush=True)
+    assert err < {"fp32": 1e-5, "bf16x3": 1e-4}[prec]
+    fixed.close()
+    jobs = problems(w, 5, 3)
+    batch = gmmpa.Batch(plan, slots=2, M=w.M)
+    inputs = [(0, to_dev(torch, A0, prec), L, dz, i) for i, (A0, L, dz) in enumerate(jobs)]
+    torch.cuda.synchronize()
+    res = gmmpa.run_batches([batch], inputs)
+    for i, (A0, L, dz) in enumerate(jobs):
+        rc, st, out = res[i]
+        refi, rst, rrc = solo(plan, torch, prec, A0, L, dz, w.M)
+        assert rc == rrc
+        assert np.array_equal(out.cpu().numpy(), refi), i
+        for k in KEYS:
+            assert st[k] == rst[k], k
+    batch.close()
+    plan.close()
+
+
 def test_batches_on_two_streams_equal_solo(torch_gpu):
     """Two plans of different shape (3 modes / 2^10 samples, Kerr; 6 modes /
     2^13, Raman) on their own streams, their rounds queued together."""
