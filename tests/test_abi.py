@@ -123,3 +123,84 @@ def test_null_arguments(lib):
     assert lib.gmm_plan_destroy(None) == 0
     assert lib.gmm_plan_device_bytes(None) == 0
     assert lib.gmm_plan_rank(None) == 0
+
+
+DRIVER_C = r"""
+#include <stdio.h>
+#include <string.h>
+#include "gmmpa.h"
+static double S[81], B[9], H[256];
+static int expect(int got, int want, const char* what) {
+  if (got != want) { printf("FAIL %s: %d != %d (%s)\n", what, got, want, gmm_last_error()); return 1; }
+  if (got < 0 && strlen(gmm_last_error()) == 0) { printf("FAIL %s: no message\n", what); return 1; }
+  return 0;
+}
+int main(void) {
+  int bad = 0;
+  gmm_params p; memset(&p, 0, sizeof p);
+  p.n_modes = 3; p.nt = 256; p.n_beta = 3; p.dt = 1e-14; p.omega0 = 1.8e15; p.n2 = 2.3e-20; p.fR = 0.0;
+  p.precision = GMM_FP32; p.tol = 1e-6; p.max_iter = 20;
+  for (int i = 0; i < 81; ++i) S[i] = 1.0;
+  gmm_plan h = 0;
+  gmm_params q = p; q.nt = 100;  bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_ARG, "nt");
+  q = p; q.n_modes = 23;         bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_UNSUPPORTED, "modes");
+  q = p; q.fR = 0.18;            bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_ARG, "hR");
+  q = p; q.factor_policy = 1; S[1] = 2.0;
+  bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_TENSOR, "symmetry");
+  S[1] = 1.0;
+  q = p; q.fR = 0.18; for (int i = 0; i < 256; ++i) H[i] = 0.0;
+  bad += expect(gmm_plan_create(&h, &q, B, S, 0, H, 0) < 0, 1, "zero h_R or no device");
+  bad += expect(gmm_plan_create(0, &p, B, S, 0, 0, 0), GMM_ERR_ARG, "null out");
+  bad += expect(gmm_propagate(0, 0, 1.0, 1.0, 1, 0, 0), GMM_ERR_ARG, "propagate null");
+  bad += expect(gmm_propagate_rk4ip(0, 0, 1.0, 1.0, 0, 0), GMM_ERR_ARG, "rk4ip null");
+  bad += expect(gmm_nonlinear(0, 0, 1, 0), GMM_ERR_ARG, "nonlinear null");
+  bad += expect(gmm_nonlinear_noalloc(0, 0, 1, 0), GMM_ERR_ARG, "noalloc null");
+  bad += expect(gmm_plan_autotune(0, 1, 0, 0, 0), GMM_ERR_ARG, "autotune null");
+  bad += expect(gmm_plan_set_contraction(0, 0), GMM_ERR_ARG, "set_contraction null");
+  gmm_batch b = 0;
+  bad += expect(gmm_batch_create(&b, 0, 1, 10), GMM_ERR_ARG, "batch null plan");
+  bad += expect(gmm_batch_launch(0), GMM_ERR_ARG, "batch launch null");
+  int n = 0; long long tags[1];
+  bad += expect(gmm_batch_wait(0, tags, 0, 0, 1, &n), GMM_ERR_ARG, "batch wait null");
+  bad += expect(gmm_batch_destroy(0), GMM_OK, "batch destroy null");
+  bad += expect(gmm_plan_destroy(0), GMM_OK, "plan destroy null");
+  printf(bad ? "driver: %d failures\n" : "driver: ok\n", bad);
+  return bad != 0;
+}
+"""
+
+
+@pytest.mark.slow
+def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The driver's host code (argument validation, tensor checks, the failure
+    and clean-up paths of plan creation) built with AddressSanitizer and
+    UndefinedBehaviorSanitizer on the host side only, linked with the library's
+    kernel objects and run by a small C program that calls through the C ABI
+    (no GPU needed: every call fails before device work, or at the first HIP
+    call when there is no device)."""
+    from paper_1708_05324_amd import build
+    hipcc = build.HIPCC
+    objs = [os.path.join(build.BUILD, f.replace(".hip", ".o")) for f in build.SOURCES if f != "gmmpa.hip"]
+    if not all(os.path.exists(o) for o in objs):
+        build.build(verbose=False)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-g"]
+    drv_obj = tmp_path / "gmmpa_san.o"
+    subprocess.run([hipcc, *build.CFLAGS, *san, "-c", os.path.join(build.CSRC, "gmmpa.hip"), "-o", str(drv_obj)],
+                   check=True, capture_output=True)
+    lib = tmp_path / "libgmmpa_san.so"
+    subprocess.run([hipcc, "-shared", "-fPIC", f"--offload-arch={build.ARCH}", "-fsanitize=address,undefined",
+                    str(drv_obj), *objs, "-o", str(lib)], check=True, capture_output=True)
+    src = tmp_path / "driver.c"
+    src.write_text(DRIVER_C)
+    exe = tmp_path / "driver"
+    subprocess.run(["/opt/rocm/llvm/bin/clang", "-fsanitize=address,undefined", "-g", "-I",
+                    os.path.join(ROOT, "include"), str(src), str(lib), "-Wl,-rpath," + str(tmp_path), "-o", str(exe)],
+                   check=True, capture_output=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1",
+               HIP_VISIBLE_DEVICES="")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0
+    assert "driver: ok" in r.stdout
+    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr
