@@ -32,7 +32,8 @@ struct BatchSlot {
   void* psi;          // [M][N][Nt] sub-step iterates (close: its row m - 1 is the source)
   void* I0_keep;      // [N][Nt] kept I_0
   void* dst;          // close: psi(z0 + m dz) goes here (the slot's psi_0)
-  const void* Em;     // close: exp(D_w m dz) row of the slot's table
+  const void* Em;     // close: exp(D_w m dz) row of the slot's table (NULL: lab-frame iterates, a copy)
+  const void* E;      // trapezoid with lab-frame storage: the slot's table [M + 1][N][Nt] (NULL: psi frame)
   double* partials;   // [trapz_blocks(N Nt)][2] FP64 partial sums of the norm
   Ctrl* ctrl;         // the slot's control block
   double dz;

@@ -1485,6 +1485,68 @@ __device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, co
   }
 }
 
+// Lab-frame storage (used when the gain and coupling terms are off): the
+// iterates are kept as exp(D_w z_j) psi_j, the fields the next evaluation
+// transforms to time as they are, and the evaluation hands over
+// i gamma^ (1 + s w/w0) F{NL_j} without exp(-D_w z_j).  This trapezoid applies
+// exp(-D_w z_j) to those integrands and exp(D_w z_j) to the new iterates (both
+// factors read once from the table, E row 0 = 1); the relative change is
+// measured on the stored fields (|exp(D z)| = 1: the same norm to rounding).
+//   Nl  : the iteration's spectral outputs: first = 1: rows 0..M (row 0 is I_0);
+//         else rows 1..M of the sub-steps j = 1..M at I + (j - 1) nn, and I_0 kept
+//   psi : [M][N][Nt] stored iterates exp(D z_j) psi_j, row j - 1 = sub-step j
+template <typename T>
+__device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0,
+                                                const cplx<T>* __restrict__ I, cplx<T>* __restrict__ psi,
+                                                cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
+                                                int first, int M, long nn, T dz, double* __restrict__ partials) {
+  __shared__ double red[2][256];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0, s = 0.0;
+  if (e < nn) {
+    const cplx<T> p0 = psi0[e];
+    const cplx<T> i0 = I0[e];
+    if (first) I0_keep[e] = i0;
+    const cplx<T> h0 = cscale(i0, T(0.5));
+    cplx<T> run = {0, 0};
+    for (int j = 0; j < M; ++j) {
+      const cplx<T> ej = E[(size_t)(j + 1) * nn + e];
+      const cplx<T> ij = cmul(I[(size_t)j * nn + e], cplx<T>{ej.re, -ej.im});
+      cplx<T> acc = cadd(cadd(h0, run), cscale(ij, T(0.5)));
+      const cplx<T> nw = cmul(cplx<T>{p0.re + dz * acc.re, p0.im + dz * acc.im}, ej);
+      run = cadd(run, ij);
+      const cplx<T> old = first ? cmul(p0, ej) : psi[(size_t)j * nn + e];
+      const double dr = (double)nw.re - (double)old.re, di = (double)nw.im - (double)old.im;
+      d += dr * dr + di * di;
+      s += (double)nw.re * nw.re + (double)nw.im * nw.im;
+      psi[(size_t)j * nn + e] = nw;
+    }
+  }
+  red[0][threadIdx.x] = d;
+  red[1][threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = red[0][0];
+    partials[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trapz_lab(
+    const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
+    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E, int first, int M,
+    long nn, T dz, double* __restrict__ partials, const Ctrl* ctrl) {
+  if (skip_iteration(ctrl)) return;
+  trapz_lab_block<T>(psi0, I0, I, psi, I0_keep, E, first, M, nn, dz, partials);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_trapz(
     const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
@@ -1507,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, 
     ctrl->pad = 0;
   }
   if (e >= nn) return;
-  dst[e] = cmul(src[e], Em[e]);
+  dst[e] = Em != nullptr ? cmul(src[e], Em[e]) : src[e];  // no factor: lab-frame iterates are already advanced
 }
 
 // ---------------------------------------------------------------------------
@@ -1522,10 +1584,11 @@ __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, 
 // bit for bit that of the same propagation run alone.
 // (BatchRow and BatchSlot are defined in gmm_common.hpp.)
 
+// lab = 1: lab-frame storage (rows from stored iterates take no factor; spectral outputs keep none).
 template <typename T, int LOGN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time_b(
     const BatchRow* __restrict__ rows, const cplx<T>* psi0, const cplx<T>* psi, const cplx<T>* __restrict__ E,
-    cplx<T>* A, int M, const cplx<T>* __restrict__ tw) {
+    cplx<T>* A, int M, const cplx<T>* __restrict__ tw, int lab) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   __shared__ T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
@@ -1533,21 +1596,21 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
   const size_t nn = (size_t)N * S::N;
   const cplx<T>* src = (d.src < 0 ? psi0 + (size_t)d.slot * nn : psi + ((size_t)d.slot * M + d.src) * nn) +
                        (size_t)p * S::N;
-  const cplx<T>* ph = E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
+  const cplx<T>* ph = (lab && d.src >= 0) ? nullptr : E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
   phase_to_time_row<T, LOGN>(src, ph, A + ((size_t)r * N + p) * S::N, lds, threadIdx.x, tw);
 }
 
 template <typename T, int LOGN>
 __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out_b(
     const BatchRow* __restrict__ rows, cplx<T>* W, const cplx<T>* __restrict__ E, int M, double domega,
-    double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw) {
+    double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw, int lab) {
   using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
   __shared__ T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
   const BatchRow d = rows[r];
   const size_t nn = (size_t)N * S::N;
   cplx<T>* row = W + ((size_t)r * N + p) * S::N;
-  const cplx<T>* ph = E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
+  const cplx<T>* ph = lab ? nullptr : E + ((size_t)d.slot * (M + 1) + d.ej) * nn + (size_t)p * S::N;
   spectral_out_row<T, LOGN>(row, row, ph, domega, gscale, inv_omega0, shock, lds, threadIdx.x, tw);
 }
 
@@ -1555,8 +1618,12 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>
 template <typename T>
 __global__ __launch_bounds__(256) void k_trapz_b(const BatchSlot* __restrict__ slots, long nn) {
   const BatchSlot d = slots[blockIdx.y];
-  trapz_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
-                 (cplx<T>*)d.I0_keep, d.first, d.m, nn, (T)d.dz, d.partials);
+  if (d.E != nullptr)  // lab-frame storage
+    trapz_lab_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
+                       (cplx<T>*)d.I0_keep, (const cplx<T>*)d.E, d.first, d.m, nn, (T)d.dz, d.partials);
+  else
+    trapz_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
+                   (cplx<T>*)d.I0_keep, d.first, d.m, nn, (T)d.dz, d.partials);
 }
 
 // grid (trapz_blocks(nn), slots closing): psi_0 <- Em .* psi_{m}, and a fresh control block
@@ -1573,7 +1640,7 @@ __global__ __launch_bounds__(256) void k_close_b(const BatchSlot* __restrict__ s
   }
   if (e >= nn) return;
   const cplx<T>* src = (const cplx<T>*)d.psi + (size_t)(d.m - 1) * nn;
-  ((cplx<T>*)d.dst)[e] = cmul(src[e], ((const cplx<T>*)d.Em)[e]);
+  ((cplx<T>*)d.dst)[e] = d.Em != nullptr ? cmul(src[e], ((const cplx<T>*)d.Em)[e]) : src[e];
 }
 
 // ---------------------------------------------------------------------------

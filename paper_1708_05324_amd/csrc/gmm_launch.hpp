@@ -46,9 +46,11 @@ struct Launch {
   static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const cplx<T>* E, int N, int count,
                                  int j0, double domega, double gscale, double inv_omega0, int shock,
                                  const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
+  // E != nullptr: lab-frame iterates (the phase table [M + 1][N][Nt] is applied inside the trapezoid)
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
-                          int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s);
-  // dst = Em .* src; with ctrl, also resets the control block for the next large step
+                          int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s,
+                          const cplx<T>* E = nullptr);
+  // dst = Em .* src (Em = nullptr: a copy); with ctrl, also resets the control block for the next large step
   static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl, hipStream_t s);
   // General-tensor route: pair rows [count][KD][Nt] (x, y and, with Raman, xr, yr), then C = G B and NL.
   static hipError_t pairs_dense(int logn, bool raman, const cplx<T>* A, T* Bd, const int2* pairs, int N, int Np,
@@ -72,11 +74,11 @@ struct Launch {
   // Batched rounds (several propagations of one plan): R rows listed in `rows`, per-slot buffers at fixed
   // strides (psi0 [S][N][Nt], psi [S][M][N][Nt], E [S][M + 1][N][Nt]); work rows [R][N][Nt].
   static hipError_t phase_to_time_b(int logn, const BatchRow* rows, const cplx<T>* psi0, const cplx<T>* psi,
-                                    const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw,
+                                    const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw, int lab,
                                     hipStream_t s);
   static hipError_t spectral_out_b(int logn, const BatchRow* rows, cplx<T>* W, const cplx<T>* E, int N, int R, int M,
                                    double domega, double gscale, double inv_omega0, int shock, const cplx<T>* tw,
-                                   hipStream_t s);
+                                   int lab, hipStream_t s);
   static hipError_t trapz_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s);
   static hipError_t close_b(const BatchSlot* slots, int nslots, long nn, hipStream_t s);
 };

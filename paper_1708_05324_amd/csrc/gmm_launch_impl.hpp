@@ -255,9 +255,13 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
 template <typename T>
 hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi,
                             cplx<T>* I0_keep, int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl,
-                            hipStream_t s) {
-  hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, first, M, nn,
-                     dz, partials, ctrl);
+                            hipStream_t s, const cplx<T>* E) {
+  if (E != nullptr)
+    hipLaunchKernelGGL((k_trapz_lab<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, E, first,
+                       M, nn, dz, partials, ctrl);
+  else
+    hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, first, M,
+                       nn, dz, partials, ctrl);
   return hipGetLastError();
 }
 
@@ -344,13 +348,13 @@ hipError_t Launch<T>::finish_H(const cplx<double>* H, cplx<T>* Gs, int nt, doubl
 
 template <typename T>
 hipError_t Launch<T>::phase_to_time_b(int logn, const BatchRow* rows, const cplx<T>* psi0, const cplx<T>* psi,
-                                      const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw,
+                                      const cplx<T>* E, cplx<T>* A, int N, int R, int M, const cplx<T>* tw, int lab,
                                       hipStream_t s) {
   if (R < 1) return hipSuccess;
   GMM_LOGN_SWITCH(logn, {
     using S = FftShape<LOGN, (int)sizeof(T)>;
     hipLaunchKernelGGL((k_phase_to_time_b<T, LOGN>), dim3(N, R), dim3(S::THREADS), 0, s, rows, psi0, psi, E, A, M,
-                       tw);
+                       tw, lab);
   });
   return hipGetLastError();
 }
@@ -358,12 +362,12 @@ hipError_t Launch<T>::phase_to_time_b(int logn, const BatchRow* rows, const cplx
 template <typename T>
 hipError_t Launch<T>::spectral_out_b(int logn, const BatchRow* rows, cplx<T>* W, const cplx<T>* E, int N, int R,
                                      int M, double domega, double gscale, double inv_omega0, int shock,
-                                     const cplx<T>* tw, hipStream_t s) {
+                                     const cplx<T>* tw, int lab, hipStream_t s) {
   if (R < 1) return hipSuccess;
   GMM_LOGN_SWITCH(logn, {
     using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
     hipLaunchKernelGGL((k_spectral_out_b<T, LOGN>), dim3(N, R), dim3(S::THREADS), 0, s, rows, W, E, M, domega, gscale,
-                       inv_omega0, shock, tw);
+                       inv_omega0, shock, tw, lab);
   });
   return hipGetLastError();
 }

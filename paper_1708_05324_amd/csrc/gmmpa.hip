@@ -243,6 +243,10 @@ void free_workspace(gmm_plan_s* P) {
 
 size_t field_bytes(const gmm_plan_s* P) { return (size_t)P->N * P->nt * 2 * P->esz; }
 
+// The MPA keeps its sub-step iterates in the lab frame, exp(D_w z_j) psi_j, when the linear operator is the
+// diagonal dispersion alone (no gain, no linear coupling): the transforms to and from time then read no phase.
+bool lab_frame(const gmm_plan_s* P) { return !P->gain_on && !P->coupling_on && !P->cpl_exact; }
+
 // Pair-integral partials and gain matrices for `cap` sub-steps (only with the gain term on).
 int ensure_gain_workspace(gmm_plan_s* P, int cap) {
   if (!(P->gain_on || P->coupling_on) || cap <= P->gain_cap) return GMM_OK;
@@ -492,14 +496,17 @@ struct Runner {
     const cplx<T>* E = dz != 0.0 ? (const cplx<T>*)P->E : nullptr;
     // coupled linear operator: psi is in the eigenbasis; the modes are U (exp(i lam z) psi)
     const bool mix = P->cpl_exact && E != nullptr;
+    // lab-frame iterates (MPA without gain and coupling terms): stored sub-step fields already carry
+    // exp(D z_j), and the outputs keep the frame (the trapezoid applies exp(-D z_j))
+    const bool lab = E != nullptr && lab_frame(P);
     if (mix && doA) {
       GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::mode_mix(false, psi, jrows, W, (const cplx<T>*)P->Uc, E, j0, P->N,
                                                       P->nt, count, ctrl, P->stream));
       GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, W, P->N, W, nullptr, P->N, count, j0, tw(),
                                                            ctrl, P->stream));
     } else if (doA) {
-      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, E, P->N, count, j0, tw(), ctrl,
-                                                           P->stream));
+      GMM_LAUNCH(P, GMM_PROF_PHASE, Launch<T>::phase_to_time(P->logn, psi, jrows, W, lab && jrows != 0 ? nullptr : E,
+                                                           P->N, count, j0, tw(), ctrl, P->stream));
     }
     const bool linear_terms = P->gain_on || P->coupling_on;
     if (linear_terms && doA) {  // pair integrals of the sub-step fields (saturation), then the matrices Mg
@@ -516,7 +523,7 @@ struct Runner {
       if (rc_mid) return rc_mid;
     }
     if (!doB) return GMM_OK;
-    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, mix ? nullptr : E, P->N, count, j0,
+    GMM_LAUNCH(P, GMM_PROF_SPECTRAL, Launch<T>::spectral_out(P->logn, W, out, mix || lab ? nullptr : E, P->N, count, j0,
                                                            P->domega, P->gamma_hat / P->nt, 1.0 / P->prm.omega0,
                                                            P->prm.self_steepening, tw(), ctrl, P->stream));
     if (mix)  // back to the eigenbasis, then exp(-i lam z)
@@ -542,7 +549,7 @@ struct Runner {
     const cplx<T>* I = first ? W + nn : W;
     GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
                                                    (cplx<T>*)P->I0, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl,
-                                                   P->stream));
+                                                   P->stream, lab_frame(P) ? (const cplx<T>*)P->E : nullptr));
     GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol,
                                                         P->prm.fixed_iters, P->prm.max_iter, P->stream));
     return GMM_OK;
@@ -662,7 +669,8 @@ struct Runner {
       // A~(z0 + m dz) = exp(D m dz) psi_m (coupled operator: exp(i lam m dz) psi_m in the eigenbasis, which is
       // also the next large step's psi(z0) there)
       GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
-                                                   (const cplx<T>*)P->E + (size_t)m * nn, nn, P->ctrl, P->stream));
+                                                   lab_frame(P) ? nullptr : (const cplx<T>*)P->E + (size_t)m * nn, nn,
+                                                   P->ctrl, P->stream));
       s.large_steps++;
       s.small_steps += m;
       done += m;
@@ -1567,7 +1575,7 @@ struct BatchRunner {
       d = gmm::BatchSlot{};
       d.psi = at(B->psi, (size_t)s * M);
       d.dst = at(B->psi0, s);
-      d.Em = at(B->E, (size_t)s * (M + 1) + q.m);
+      d.Em = nullptr;  // lab-frame iterates: the last one is the field at the step's end
       d.ctrl = B->ctrl + s;
       d.m = q.m;
       closing.push_back(s);
@@ -1602,6 +1610,7 @@ struct BatchRunner {
       d.I = at(B->work, q.first ? o + 1 : o);
       d.psi = at(B->psi, (size_t)s * M);
       d.I0_keep = at(B->I0, s);
+      d.E = at(B->E, (size_t)s * (M + 1));
       d.partials = B->partials + (size_t)s * 2 * B->nblk;
       d.ctrl = B->ctrl + s;
       d.dz = q.dz;
@@ -1631,14 +1640,14 @@ struct BatchRunner {
       ws.plane_words = (size_t)ws.cap * gmm::kBf16Kpad * P->nt / 2;
       cplx<T>* W = (cplx<T>*)B->work;
       GMM_HIP(Launch<T>::phase_to_time_b(P->logn, B->rows_d, (const cplx<T>*)B->psi0, (const cplx<T>*)B->psi,
-                                         (const cplx<T>*)B->E, W, P->N, R, M, tw(), P->stream));
+                                         (const cplx<T>*)B->E, W, P->N, R, M, tw(), 1, P->stream));
       const bool prof_on = P->prof.on;  // per-kernel events are for gmm_propagate
       P->prof.on = false;
       const int rc = Runner<T>{P}.mid(R, ws, nullptr, true, true);
       P->prof.on = prof_on;
       if (rc) return rc;
       GMM_HIP(Launch<T>::spectral_out_b(P->logn, B->rows_d, W, (const cplx<T>*)B->E, P->N, R, M, P->domega,
-                                        P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(),
+                                        P->gamma_hat / P->nt, 1.0 / P->prm.omega0, P->prm.self_steepening, tw(), 1,
                                         P->stream));
       GMM_HIP(Launch<T>::trapz_b(B->slots_d, ns, (long)n, P->stream));
       GMM_HIP(gmm::launch_norm_final_b(B->slots_d, ns, B->nblk, P->prm.tol, P->prm.fixed_iters, P->prm.max_iter,
