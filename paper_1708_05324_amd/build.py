@@ -1,7 +1,8 @@
 """Build libgmmpa.so (HIP, gfx950) in-tree: ``python -m paper_1708_05324_amd.build``.
 
 Each translation unit is compiled by hipcc in parallel, then linked into
-paper_1708_05324_amd/libgmmpa.so.  Packed FP32 instructions are disabled for
+paper_1708_05324_amd/libgmmpa.so (with rocBLAS, which runs the two plain GEMMs
+of the wide rank-r route).  Packed FP32 instructions are disabled for
 device code (-packed-fp32-ops); hipcc's host pass warns that it does not know
 the feature, which is harmless.
 """
@@ -17,11 +18,12 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgmmpa.so")
-SOURCES = ["gmm_kern_f32.hip", "gmm_kern_f64.hip", "gmmpa.hip"]
+SOURCES = ["gmm_kern_f32.hip", "gmm_kern_f64.hip", "gmm_wide.hip", "gmmpa.hip"]
 ARCH = os.environ.get("GMM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result", "-I", INCLUDE]
+LDFLAGS = ["-L/opt/rocm/lib", "-lrocblas"]
 
 
 def _compile(src: str) -> str:
@@ -38,7 +40,7 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, *LDFLAGS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")

@@ -126,6 +126,24 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
                              int max_iter, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
+
+// Wide rank-r route (complex64 fields, N <= wide_max_modes(); gmm_wide.hip).
+int wide_max_modes();
+// B_Q(t) = Re(A_m A_n^*) for the Np pairs: BF16 planes [count][2][Np][Nt] bf16, else FP32 [count][Np][Nt].
+hipError_t launch_pairs_wide(bool bf16, const cplx<float>* A, void* Bout, int N, int Np, int Nt, int count,
+                             const Ctrl* ctrl, hipStream_t s);
+// FP32 rows [count][rows][Nt] -> bf16 planes [count][2][rows][Nt] (hi, lo).
+hipError_t launch_split_rows(const float* Y, void* planes, int rows, int Nt, int count, const Ctrl* ctrl,
+                             hipStream_t s);
+// NL_p(t) = sum_l C_(p,l)(t) A_l(t), C [count][Np][Nt] FP32; NL overwrites A in place.
+hipError_t launch_fold_wide(const float* C, cplx<float>* A_NL, int N, int Np, int Nt, int count, const Ctrl* ctrl,
+                            hipStream_t s);
+// Per sub-step, out [n][m] = W X with X [k][m] (BF16: planes [2][k][m], Wst [n][2k] = [W^hi W^hi], Wlo [n][k];
+// FP32: X [k][m], Wst [n][k]); rocBLAS on stream s.
+hipError_t wide_gemm(void* handle, bool bf16, int m, int n, int k, const void* X, const void* Wst, const void* Wlo,
+                     float* out, int count, hipStream_t s);
+int wide_blas_create(void** handle);
+void wide_blas_destroy(void* handle);
 // Norm reduction and stop decision for each slot of a batched round (one block per slot).
 hipError_t launch_norm_final_b(const BatchSlot* slots, int nslots, int nblocks, double tol, int fixed_iters,
                                int max_iter, hipStream_t s);

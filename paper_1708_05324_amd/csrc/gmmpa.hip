@@ -170,6 +170,13 @@ struct gmm_plan_s {
   void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
   void* Vlo = nullptr;
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
+  // wide rank-r route (complex64 fields, N up to 55): both products on rocBLAS, see gmm_wide.hip
+  bool wide = false;
+  void* blas = nullptr;    // rocblas_handle
+  void* Wv = nullptr;      // BF16: [rq][2 Np] = [V^hi V^hi]; FP32: [rq][Np] V
+  void* Wv_lo = nullptr;   // BF16: [rq][Np] V^lo
+  void* Wu = nullptr;      // BF16: [Np][2 rq] = [U^hi U^hi]; FP32: [Np][rq] U
+  void* Wu_lo = nullptr;   // BF16: [Np][rq] U^lo
   // overlap-save form of the Raman convolution (short Raman response)
   int os_lh = 0, os_v = 0;  // kernel taps, outputs per 2^11-point segment (0: full-row transforms)
   void* Gos = nullptr;      // [2^11] segment filter DFT_{+}(g) / 2^11, field precision
@@ -273,6 +280,8 @@ int ensure_gain_workspace(gmm_plan_s* P, int cap) {
 // B' for `cap` sub-steps: [cap][Np][Nt] reals, or two bf16 planes [cap][Kpad/8][Nt][8].
 size_t bp_bytes(const gmm_plan_s* P, int cap) {
   if (P->dense) return (size_t)cap * P->KD * P->nt * P->esz;
+  // wide route: [cap][Np][Nt] 4-byte words (B: two bf16 planes or FP32 rows, later C), then Y' [cap][RQ][Nt]
+  if (P->wide) return (size_t)cap * (P->Np + P->rq) * P->nt * 4;
   if (P->bf16) return 2 * (size_t)cap * gmm::kBf16Kpad * P->nt * 2;
   // packed route: [cap][Np][Nt]; rank-r route: Y' [cap][RQ][Nt] (RQ can exceed Np for small Np)
   const int rows = P->factored ? std::max(P->Np, P->rq) : P->Np;
@@ -340,7 +349,7 @@ struct ContractCand {
 };
 std::vector<ContractCand> contraction_candidates(const gmm_plan_s* P) {
   std::vector<ContractCand> c;
-  if (P->fp64 || P->dense) return c;
+  if (P->fp64 || P->dense || P->wide) return c;
   if (P->factored && !P->bf16) {
     for (int b : {1, 2}) c.push_back({0, b});
     if (P->rt <= 2)
@@ -366,6 +375,43 @@ struct Runner {
   // halves before / from the contraction.
   int mid(int count, const EvalWs& ws, const Ctrl* ctrl, bool doA, bool doB) {
     cplx<T>* W = (cplx<T>*)ws.work;
+    if (P->wide) {  // pair rows; Y = V B; Y' = g * Y; C = U Y'; fold (the products on rocBLAS, in the second half)
+      if constexpr (std::is_same<T, float>::value) {
+        float* BC = (float*)ws.Bp;                                       // B rows, later C
+        float* Yp = (float*)ws.Bp + (size_t)ws.cap * P->Np * P->nt;     // Y' [cap][RQ][Nt]
+        float* Y = (float*)ws.Y;
+        if (doA)
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_pairs_wide(P->bf16, W, BC, P->N, P->Np, P->nt, count, ctrl,
+                                                               P->stream));
+        if (!doB) return GMM_OK;
+        GMM_LAUNCH(P, GMM_PROF_PROJECT, gmm::wide_gemm(P->blas, P->bf16, P->nt, P->rq, P->Np, BC, P->Wv, P->Wv_lo, Y,
+                                                       count, P->stream));
+        const float* Yc = Y;
+        if (P->raman) {
+          const int R = P->rank + (P->rank & 1);
+          if (P->os_lh)
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<float>::conv_os(Y, Yp, R, P->rq, count, P->nt, P->os_lh, P->os_v,
+                                                                 (const cplx<float>*)P->Gos,
+                                                                 (const cplx<float>*)P->twos, ctrl, P->stream));
+          else
+            GMM_LAUNCH(P, GMM_PROF_PAIRS, Launch<float>::conv(P->logn, Y, Yp, R, P->rq, count,
+                                                              (const cplx<float>*)P->Hs, tw(), ctrl, P->stream));
+          Yc = Yp;
+        }
+        const void* X = Yc;
+        if (P->bf16) {  // Y' -> bf16 planes, into whichever of Y and the Y' region Yc is not
+          void* planes = P->raman ? (void*)Y : (void*)Yp;
+          GMM_LAUNCH(P, GMM_PROF_PAIRS, gmm::launch_split_rows(Yc, planes, P->rq, P->nt, count, ctrl, P->stream));
+          X = planes;
+        }
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::wide_gemm(P->blas, P->bf16, P->nt, P->Np, P->rq, X, P->Wu, P->Wu_lo, BC,
+                                                        count, P->stream));
+        GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_fold_wide(BC, W, P->N, P->Np, P->nt, count, ctrl, P->stream));
+        return GMM_OK;
+      } else {
+        return fail(GMM_ERR_UNSUPPORTED, "internal: wide route with complex128 fields");
+      }
+    }
     if (P->dense) {  // general tensors: real pair rows, then C = G B and the complex projection
       bool os_done = false;
       if constexpr (std::is_same<T, float>::value) {
@@ -1125,6 +1171,115 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
   return GMM_OK;
 }
 
+// Wide rank-r route: S^ = U V from a pivoted Cholesky factorisation of the
+// symmetric pair matrix a_ij = S_(pair i)(pair j).  For the overlap tensor of
+// Eq. (2) a is the Gram matrix of the pair products F_m F_n, so it is positive
+// semi-definite and its Cholesky factor L [Np][r] has the numerical rank r as
+// column count.  U = L and V = L^T diag(w) (w = 1 for m = n, 2 otherwise) give
+// U V = a diag(w) = S^.  Columns are added while the largest remaining
+// diagonal exceeds 1e-13 of the largest initial one; the factor is kept only if
+// U V reproduces S^ to 1e-12 of its largest entry (else GMM_ERR_TENSOR).
+int factor_wide(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs) {
+  const int Np = P->Np, N = P->N;
+  auto S4 = [&](int a, int b, int c, int d) { return SK[(((size_t)a * N + b) * N + c) * N + d]; };
+  std::vector<double> a((size_t)Np * Np);
+  double smax = 0;
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) {
+      a[(size_t)i * Np + j] = S4(pairs[i].x, pairs[i].y, pairs[j].x, pairs[j].y);
+      smax = std::max(smax, std::fabs(a[(size_t)i * Np + j]));
+    }
+  for (int i = 0; i < Np; ++i)
+    for (int j = i + 1; j < Np; ++j)
+      if (std::fabs(a[(size_t)i * Np + j] - a[(size_t)j * Np + i]) > 1e-12 * smax)
+        return fail(GMM_ERR_TENSOR, "the wide rank-r route needs S_plmn = S_mnpl as well");
+  std::vector<double> d(Np), L;  // L: column c at L[c * Np .. c * Np + Np)
+  std::vector<char> used(Np, 0);
+  double dmax0 = 0;
+  for (int i = 0; i < Np; ++i) dmax0 = std::max(dmax0, d[i] = a[(size_t)i * Np + i]);
+  int r = 0;
+  while (r < Np) {
+    int piv = -1;
+    double best = 0;
+    for (int i = 0; i < Np; ++i)
+      if (!used[i] && d[i] > best) best = d[piv = i];
+    if (piv < 0 || best <= 1e-13 * dmax0) break;
+    used[piv] = 1;
+    const double sq = std::sqrt(best);
+    L.resize((size_t)(r + 1) * Np);
+    double* col = &L[(size_t)r * Np];
+    for (int i = 0; i < Np; ++i) {
+      if (used[i]) {
+        col[i] = i == piv ? sq : 0.0;
+        continue;
+      }
+      double x = a[(size_t)i * Np + piv];
+      for (int c = 0; c < r; ++c) x -= L[(size_t)c * Np + i] * L[(size_t)c * Np + piv];
+      col[i] = x / sq;
+      d[i] -= col[i] * col[i];
+    }
+    ++r;
+  }
+  if (r < 1 || r > 256) return fail(GMM_ERR_TENSOR, "the wide rank-r route found rank " + std::to_string(r) +
+                                                      " (1..256 supported)");
+  double err = 0, ref = 0;
+  for (int i = 0; i < Np; ++i)
+    for (int j = 0; j < Np; ++j) {
+      double x = 0;
+      for (int c = 0; c < r; ++c) x += L[(size_t)c * Np + i] * L[(size_t)c * Np + j];
+      const double w = pairs[j].x == pairs[j].y ? 1.0 : 2.0;
+      err = std::max(err, std::fabs(w * x - w * a[(size_t)i * Np + j]));
+      ref = std::max(ref, std::fabs(w * a[(size_t)i * Np + j]));
+    }
+  if (!(err <= 1e-12 * ref))
+    return fail(GMM_ERR_TENSOR, "the pair matrix is not positive semi-definite to rounding (wide rank-r route)");
+  const int rq = ((r + 15) / 16) * 16;
+  auto Uv = [&](int Q, int rho) { return L[(size_t)rho * Np + Q]; };
+  auto Vv = [&](int rho, int Q) { return L[(size_t)rho * Np + Q] * (pairs[Q].x == pairs[Q].y ? 1.0 : 2.0); };
+  int rc;
+  if (P->bf16) {
+    std::vector<uint16_t> wv((size_t)rq * 2 * Np, 0), wvl((size_t)rq * Np, 0), wu((size_t)Np * 2 * rq, 0),
+        wul((size_t)Np * rq, 0);
+    for (int rho = 0; rho < r; ++rho)
+      for (int Q = 0; Q < Np; ++Q) {
+        const float v = (float)Vv(rho, Q), u = (float)Uv(Q, rho);
+        const uint16_t vh = host_bf16(v), uh = host_bf16(u);
+        wv[(size_t)rho * 2 * Np + Q] = wv[(size_t)rho * 2 * Np + Np + Q] = vh;
+        wvl[(size_t)rho * Np + Q] = host_bf16(v - host_bf16_value(vh));
+        wu[(size_t)Q * 2 * rq + rho] = wu[(size_t)Q * 2 * rq + rq + rho] = uh;
+        wul[(size_t)Q * rq + rho] = host_bf16(u - host_bf16_value(uh));
+      }
+    if ((rc = dev_alloc(&P->const_bytes, &P->Wv, wv.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Wv_lo, wvl.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Wu, wu.size() * 2)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Wu_lo, wul.size() * 2)))
+      return rc;
+    GMM_HIP(hipMemcpy(P->Wv, wv.data(), wv.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Wv_lo, wvl.data(), wvl.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Wu, wu.data(), wu.size() * 2, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Wu_lo, wul.data(), wul.size() * 2, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> wv((size_t)rq * Np, 0.f), wu((size_t)Np * rq, 0.f);
+    for (int rho = 0; rho < r; ++rho)
+      for (int Q = 0; Q < Np; ++Q) {
+        wv[(size_t)rho * Np + Q] = (float)Vv(rho, Q);
+        wu[(size_t)Q * rq + rho] = (float)Uv(Q, rho);
+      }
+    if ((rc = dev_alloc(&P->const_bytes, &P->Wv, wv.size() * 4)) ||
+        (rc = dev_alloc(&P->const_bytes, &P->Wu, wu.size() * 4)))
+      return rc;
+    GMM_HIP(hipMemcpy(P->Wv, wv.data(), wv.size() * 4, hipMemcpyHostToDevice));
+    GMM_HIP(hipMemcpy(P->Wu, wu.data(), wu.size() * 4, hipMemcpyHostToDevice));
+  }
+  if (gmm::wide_blas_create(&P->blas) != 0) return fail(GMM_ERR_HIP, "rocblas_create_handle failed");
+  P->wide = true;
+  P->factored = true;
+  P->rank = r;
+  P->rq = rq;
+  P->kp = Np;
+  return GMM_OK;
+}
+
 // Real coupling matrix of the general route, G [rows_pad][KD]: output rows
 // 2 (p N + l) + {0: Re C_pl, 1: Im C_pl}; columns Q (x), Np + Q (y), and with
 // Raman 2 Np + Q (xr), 3 Np + Q (yr), for the pairs Q = (m <= n):
@@ -1258,12 +1413,13 @@ void destroy(gmm_plan_s* P) {
   free_workspace(P);
   for (void* p : {(void*)P->coef, P->tw, P->Hs, P->ST, P->Shi, P->Slo, P->VT, P->UT, P->Uhi, P->Ulo, P->Vhi, P->Vlo,
                   P->G, P->Ghi, P->Glo, (void*)P->gvec, (void*)P->SRd, (void*)P->gpart, (void*)P->Mg, (void*)P->Kc,
-                  P->Uc, (void*)P->lam, P->Gos, P->twos,
+                  P->Uc, (void*)P->lam, P->Gos, P->twos, P->Wv, P->Wv_lo, P->Wu, P->Wu_lo,
                   (void*)P->pidx,
                   (void*)P->pairs, (void*)P->ctrl})
     if (p) (void)hipFree(p);
   if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
   if (P->ev) (void)hipEventDestroy(P->ev);
+  gmm::wide_blas_destroy(P->blas);
   if (P->h_partials) (void)hipHostFree(P->h_partials);
   delete P;
 }
@@ -1287,7 +1443,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (!(p->dt > 0) || !(p->omega0 > 0) || !(p->n2 >= 0) || !(p->fR >= 0 && p->fR <= 1))
     return fail(GMM_ERR_ARG, "dt, omega0 must be > 0; n2 >= 0; 0 <= fR <= 1");
   if (p->max_iter < 1 || p->fixed_iters < 0 || !(p->tol >= 0)) return fail(GMM_ERR_ARG, "bad iteration control");
-  if (p->factor_policy < 0 || p->factor_policy > 2) return fail(GMM_ERR_ARG, "factor_policy must be 0, 1 or 2");
+  if (p->factor_policy < 0 || p->factor_policy > 3) return fail(GMM_ERR_ARG, "factor_policy must be 0..3");
   if (p->s_complex != 0 && p->s_complex != 1) return fail(GMM_ERR_ARG, "s_complex must be 0 or 1");
   const double domega = 2.0 * kPi / (nt * p->dt);
   if (p->self_steepening && !(p->omega0 - domega * (nt / 2) > 0))
@@ -1296,10 +1452,19 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (raman && !hR) return fail(GMM_ERR_ARG, "hR required when fR > 0");
   const int Np = N * (N + 1) / 2;
   const int rpad = ((Np + 63) / 64) * 64;
-  if (rpad > gmm::contract_max_rows())
-    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: the contraction exceeds 256 pair rows");
-  if (bf16 && Np > gmm::kBf16Kpad)
-    return fail(GMM_ERR_UNSUPPORTED, "the BF16 split contraction supports up to 15 modes");
+  // the packed, rank-r and general routes hold up to 256 pair rows (22 modes; 15 in BF16X3); beyond, and with
+  // factor_policy 3, the wide rank-r route (complex64 fields, up to 55 modes)
+  const bool narrow_ok = rpad <= gmm::contract_max_rows() && !(bf16 && Np > gmm::kBf16Kpad);
+  const bool want_wide = p->factor_policy == 3 || (p->factor_policy == 0 && !narrow_ok);
+  if (!want_wide && rpad > gmm::contract_max_rows())
+    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes: the packed and general routes exceed 256 pair rows");
+  if (!want_wide && bf16 && Np > gmm::kBf16Kpad)
+    return fail(GMM_ERR_UNSUPPORTED, "the BF16 split packed and general routes support up to 15 modes");
+  if (want_wide && fp64)
+    return fail(GMM_ERR_UNSUPPORTED, "more than 22 modes (or factor_policy 3) needs complex64 fields: the wide "
+                                     "rank-r route runs GMM_FP32 and GMM_BF16X3");
+  if (want_wide && N > gmm::wide_max_modes())
+    return fail(GMM_ERR_UNSUPPORTED, "more than 55 modes");
   // tensors: real [N^4] or complex [N^4][2] (s_complex); S^R = S^K when SR is NULL
   const size_t n4 = (size_t)N * N * N * N;
   const bool cplxS = p->s_complex == 1;
@@ -1333,9 +1498,10 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
             break;
           }
         }
-  if (p->factor_policy == 1 && !packable)
-    return fail(GMM_ERR_TENSOR, "the packed contraction needs a real S^K = S^R with S_plmn = S_plnm = S_lpmn");
-  const bool dense = p->factor_policy == 2 || !packable;
+  if ((p->factor_policy == 1 || want_wide) && !packable)
+    return fail(GMM_ERR_TENSOR, want_wide ? "the wide rank-r route needs a real S^K = S^R with S_plmn = S_plnm = S_lpmn"
+                                          : "the packed contraction needs a real S^K = S^R with S_plmn = S_plnm = S_lpmn");
+  const bool dense = !want_wide && (p->factor_policy == 2 || !packable);
   std::vector<double> skr;  // real S^K for the packed routes
   if (!dense) {
     skr.resize(n4);
@@ -1414,14 +1580,14 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (dense) {
     rc = fp64 ? upload_dense<double>(P, sk, sr) : upload_dense<float>(P, sk, sr);
     if (rc) return bail(rc);
-  } else if (bf16 && (rc = upload_bf16_split(P, ST))) {
+  } else if (bf16 && !want_wide && (rc = upload_bf16_split(P, ST))) {
     return bail(rc);
   }
   if (raman) {  // the general route convolves with H itself; the packed routes with the blend (1 - fR) + fR H
     const double blend = dense ? 1.0 : p->fR;
     rc = fp64 ? build_raman<double>(P, hR, blend) : build_raman<float>(P, hR, blend);
     if (rc) return bail(rc);
-    if (!dense && p->factor_policy == 0) {
+    if (!dense && !want_wide && p->factor_policy == 0) {
       rc = fp64 ? try_factor<double>(P, skr.data(), pairs, ST) : try_factor<float>(P, skr.data(), pairs, ST);
       if (rc) return bail(rc);
     }
@@ -1429,6 +1595,7 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
         (rc = fp64 ? build_overlap_save<double>(P, hR, blend) : build_overlap_save<float>(P, hR, blend)))
       return bail(rc);
   }
+  if (want_wide && (rc = factor_wide(P, skr.data(), pairs))) return bail(rc);
   if (hipEventCreateWithFlags(&P->ev, hipEventDisableTiming) != hipSuccess)
     return bail(fail(GMM_ERR_HIP, "hipEventCreate failed"));
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);

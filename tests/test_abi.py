@@ -87,16 +87,23 @@ def _create(lib, prm, S=None, hR=None, SR=None, betas=None):
     (dict(dt=0.0), gmmpa.GMM_ERR_ARG),
     (dict(fR=1.5), gmmpa.GMM_ERR_ARG),
     (dict(max_iter=0), gmmpa.GMM_ERR_ARG),
-    (dict(factor_policy=3), gmmpa.GMM_ERR_ARG),
+    (dict(factor_policy=4), gmmpa.GMM_ERR_ARG),
+    (dict(factor_policy=3), gmmpa.GMM_ERR_UNSUPPORTED),     # the wide rank-r route needs complex64 fields
     (dict(s_complex=2), gmmpa.GMM_ERR_ARG),
     (dict(fR=0.18), gmmpa.GMM_ERR_ARG),                     # Raman without h_R
     (dict(self_steepening=1, dt=0.5e-15), gmmpa.GMM_ERR_ARG),   # 1 + w/w0 <= 0 on the grid
-    (dict(n_modes=23, nt=256), gmmpa.GMM_ERR_UNSUPPORTED),  # beyond 256 packed rows
-    (dict(n_modes=16, precision=2), gmmpa.GMM_ERR_UNSUPPORTED),   # BF16 split: up to 15 modes
+    (dict(n_modes=23, nt=256), gmmpa.GMM_ERR_UNSUPPORTED),  # FP64 beyond 256 packed rows
 ])
 def test_invalid_plans_are_rejected(lib, kw, code):
     rc, h = _create(lib, _params(**kw))
     assert rc == code
+    assert h.value is None
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_more_than_55_modes_is_rejected(lib, prec):
+    rc, h = _create(lib, _params(n_modes=56, precision=prec), S=np.zeros(56 ** 4))
+    assert rc == gmmpa.GMM_ERR_UNSUPPORTED
     assert h.value is None
     assert lib.gmm_last_error().decode() != ""
 
@@ -143,7 +150,10 @@ int main(void) {
   for (int i = 0; i < 81; ++i) S[i] = 1.0;
   gmm_plan h = 0;
   gmm_params q = p; q.nt = 100;  bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_ARG, "nt");
-  q = p; q.n_modes = 23;         bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_UNSUPPORTED, "modes");
+  /* refused before the tensor is read (S holds 3^4 values only) */
+  q = p; q.n_modes = 56;         bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_UNSUPPORTED, "modes");
+  q = p; q.n_modes = 23; q.precision = GMM_FP64;
+  bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_UNSUPPORTED, "fp64 modes");
   q = p; q.fR = 0.18;            bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_ARG, "hR");
   q = p; q.factor_policy = 1; S[1] = 2.0;
   bad += expect(gmm_plan_create(&h, &q, B, S, 0, 0, 0), GMM_ERR_TENSOR, "symmetry");
@@ -190,7 +200,7 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers(tmp_path):
                    check=True, capture_output=True)
     lib = tmp_path / "libgmmpa_san.so"
     subprocess.run([hipcc, "-shared", "-fPIC", f"--offload-arch={build.ARCH}", "-fsanitize=address,undefined",
-                    str(drv_obj), *objs, "-o", str(lib)], check=True, capture_output=True)
+                    str(drv_obj), *objs, *build.LDFLAGS, "-o", str(lib)], check=True, capture_output=True)
     src = tmp_path / "driver.c"
     src.write_text(DRIVER_C)
     exe = tmp_path / "driver"
