@@ -51,7 +51,8 @@ typedef enum {
   GMM_FP64 = 0,   /* complex128 fields, FP64 transforms, FP64 MFMA contraction */
   GMM_FP32 = 1,   /* complex64 fields, FP32 transforms, FP32 MFMA contraction */
   GMM_BF16X3 = 2  /* complex64 fields, FP32 transforms; contraction as S^hi B^hi + S^hi B^lo + S^lo B^hi
-                     with bf16 hi/lo splits on MFMA, FP32 accumulation (up to 15 modes) */
+                     with bf16 hi/lo splits on MFMA, FP32 accumulation (packed, rank-r and general routes up
+                     to 15 modes; the wide rank-r route up to 55) */
 } gmm_precision;
 /* With Raman and Nt >= 2^13, the Raman convolution drops the samples of h_R
  * beyond the first Lh <= 1024 once their absolute sum is at most 1e-9 (GMM_FP32,
@@ -78,7 +79,13 @@ typedef struct {
                            the general route.  1: the packed matrix S^ itself (GMM_ERR_TENSOR if the
                            tensor does not allow it).  2: the general route for any tensor: complex
                            C_pl from 2 N^2 x 4 Np real coefficients (S^K != S^R, complex S, polarised
-                           modes), NL_p = sum_l C_pl A_l */
+                           modes), NL_p = sum_l C_pl A_l.  These three hold up to 256 pair rows (22
+                           modes; 15 in GMM_BF16X3).  3, and 0 beyond those limits: the wide rank-r
+                           route, N <= 55, complex64 fields only (GMM_FP32, GMM_BF16X3): S^ = U V from
+                           a pivoted Cholesky factor of the pair matrix, which must be positive
+                           semi-definite to rounding (the overlap tensor of Eq. (2) is: it is a Gram
+                           matrix), else GMM_ERR_TENSOR; both products run as library GEMMs
+                           (rocBLAS), the pair products and the fold as kernels */
   int s_complex;        /* 0: SK and SR hold N^4 real values; 1: N^4 complex values, interleaved
                            (re, im) doubles */
 } gmm_params;
@@ -312,8 +319,9 @@ const char* gmm_last_error(void);
 /* Device bytes currently held by the plan (constants + workspace). */
 long long gmm_plan_device_bytes(gmm_plan plan);
 
-/* Rank r of the factor S^ = U V the plan contracts through (factor_policy 0,
- * Raman on, r small enough), or 0 when it uses the packed matrix itself. */
+/* Rank r of the factor S^ = U V the plan contracts through (the rank-r route:
+ * factor_policy 0, Raman on, r small enough; the wide rank-r route), or 0 when
+ * it uses the packed matrix itself or the general route. */
 int gmm_plan_rank(gmm_plan plan);
 
 /*

@@ -148,7 +148,7 @@ class Plan:
     precision: "fp64" (complex128 fields), "fp32" (complex64 fields) or "bf16x3"
     (complex64 fields, BF16 hi/lo split contraction with FP32 accumulation).
     SK, SR: real or complex [N]*4 tensors (SR None: S^R = S^K); factor_policy
-    0/1/2 picks the contraction route as documented in include/gmmpa.h.
+    0..3 picks the contraction route as documented in include/gmmpa.h.
     """
 
     def __init__(self, betas, SK, hR=None, *, nt: int, dt: float, omega0: float, n2: float, fR: float,
