@@ -172,6 +172,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
                                           if prof_window else None),
         "breakdown": breakdown,
         "rank": rank,
+        "device_bytes": plan.device_bytes(),
     }
     if lat:
         lat.sort()
@@ -372,8 +373,9 @@ def bench_serve(args) -> dict:
     the capacity measured in that run (served requests per second; a second
     stream of the same draws with the arrival times stretched)."""
     from paper_1708_05324_amd import serve, synth
-    reqs = synth.request_stream(count=args.requests, rate=args.rate, length_scale=args.serve_length_scale)
-    warm = synth.request_stream(seed=6, count=12, rate=1e4, length_scale=0.001)
+    reqs = synth.request_stream(count=args.requests, rate=args.rate, max_groups=args.max_groups,
+                                length_scale=args.serve_length_scale)
+    warm = synth.request_stream(seed=6, count=12, rate=1e4, max_groups=args.max_groups, length_scale=1e-4)
     srv = serve.Server(precision="bf16x3")
     srv.prepare(reqs)
     srv.run(warm, realtime=False)                        # code loading, first batches of several classes
@@ -386,7 +388,8 @@ def bench_serve(args) -> dict:
     return {"metric": "served GRIN propagations: p50/p99 latency and throughput under a Poisson stream",
             "unit": "ms", "value": first["latency_ms_p50"], "dtype": "bf16x3+f32 (FP64 norm)",
             "config": {"workload": "grin_serve", "requests": args.requests, "rate_per_s": args.rate,
-                       "groups": [1, 5], "modes_max": 15, "nt": [4096, 32768],
+                       "groups": [1, args.max_groups], "modes_max": args.max_groups * (args.max_groups + 1) // 2,
+                       "nt": [4096, 32768],
                        "lengths_m": [0.1 * args.serve_length_scale, 2.0 * args.serve_length_scale],
                        "energy_nJ": [1, 200], "chirp": [-5, 5], "M": 10, "slots_per_batch": srv.slots,
                        "budget_GiB": srv.budget_bytes / 2 ** 30},
@@ -444,6 +447,9 @@ def main():
                     help="only time the general-tensor route (complex S^K != S^R without index symmetry, as "
                          "polarised modes give) on the 15-mode 2^14 workload, 3 iterations per large step, and "
                          "print its own JSON line")
+    ap.add_argument("--wide", action="store_true",
+                    help="only time the wide rank-r route on 55 modes (ten Hermite-Gauss groups, rank 190) at "
+                         "Nt = 2^15 and 2^14 in the chosen precision (tolerance mode), and print its own JSON line")
     ap.add_argument("--coupling-exact", action="store_true",
                     help="only time the metric workload with a Hermitian linear coupling matrix placed in the "
                          "linear operator (per-frequency eigenbasis, mode mixing around the transforms)")
@@ -458,12 +464,14 @@ def main():
     ap.add_argument("--length-scale", type=float, default=0.05,
                     help="batched workload: fibre lengths are uniform in [0.1, 1] m times this factor")
     ap.add_argument("--serve", action="store_true",
-                    help="only run the serving workload (seeded Poisson stream of GRIN requests of 1-15 modes and "
+                    help="only run the serving workload (seeded Poisson stream of GRIN requests of 1-55 modes and "
                          "2^12-2^15 samples, BF16X3 with the FP64 norm) at the offered rate and at 0.7x the "
                          "measured capacity, and print its own JSON line")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per stream")
+    ap.add_argument("--max-groups", type=int, default=10,
+                    help="serving: Hermite-Gauss groups drawn uniformly in 1..this (10 groups = 55 modes)")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: offered requests per second")
-    ap.add_argument("--serve-length-scale", type=float, default=0.01,
+    ap.add_argument("--serve-length-scale", type=float, default=0.001,
                     help="serving: lengths are uniform in [0.1, 2] m times this factor")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (counter calibration)")
@@ -558,6 +566,27 @@ def main():
                "ms_per_large_step": round(r["ms_per_large_step"], 4)}
         if r["breakdown"]:
             out["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4) for k, v in r["breakdown"].items()}
+        print(json.dumps(out), flush=True)
+        return
+    if args.wide:
+        prec = "bf16x3" if args.precision == "fp64" else args.precision
+        lines = {}
+        for nt in (2 ** 15, 2 ** 14):
+            w = synth.wide_workload(nt)
+            r = run_gpu(prec, w, max(3, args.steps // 10), 2, 0, not args.no_profile, repeats=3)
+            lines[f"nt{nt}"] = {"small_steps_per_s": round(r["small_steps_per_s"], 2),
+                                "ms_per_large_step": round(r["ms_per_large_step"], 3),
+                                "iterations_per_large_step": round(r["iterations_per_large_step"], 3),
+                                "evaluations_per_s": round(r["evaluations_per_s"], 2), "rank": r["rank"],
+                                "dz_um": round(w.dz * 1e6, 4), "plan_device_GiB": round(r["device_bytes"] / 2 ** 30, 3)}
+            if r["breakdown"]:
+                lines[f"nt{nt}"]["kernel_ms_per_large_step_warmup"] = {k: round(v[0], 4)
+                                                                       for k, v in r["breakdown"].items()}
+        out = {"metric": "MPA steps/s, wide rank-r route at 55 modes", "unit": "small steps/s",
+               "value": lines["nt32768"]["small_steps_per_s"], "dtype": DTYPE[prec],
+               "config": {"workload": "grin55_raman_nt32768", "n_modes": 55, "M": 10, "tol": TOL[prec],
+                          "route": "wide rank-r (pair kernel, rocBLAS GEMMs V B and U Y', fold kernel)"},
+               "by_nt": lines}
         print(json.dumps(out), flush=True)
         return
     if args.general:

@@ -1,7 +1,7 @@
 """Serving loop: continuous batching of GRIN propagation requests on one GPU.
 
 Requests arrive over time (see synth.request_stream).  Each belongs to a shape
-class (Hermite-Gauss groups, samples); a class is served by batches
+class (Hermite-Gauss groups 1..10, so 1 to 55 modes; samples); a class is served by batches
 (gmm_batch_*, one plan and one HIP stream each) of a few slots.  Admission is
 by device-memory footprint: a request whose class has a free slot is admitted
 at once; otherwise a new batch of its class is created if the bytes it needs
@@ -108,13 +108,20 @@ class Server:
     def _estimate(self, cls) -> int:
         if cls in self.bytes_per_class:
             return self.bytes_per_class[cls]
-        # per slot: psi_0, I_0, M iterates, M + 1 phase rows and M + 1 work rows of N Nt complex values; per
-        # row at most 512 Nt bytes of pair rows and 256 Nt of rank-r rows; 64 MiB for the plan's constants
+        # per slot: psi_0, I_0, M iterates, M + 1 phase rows and M + 1 work rows of N Nt complex values.  Per row
+        # (sub-step of a round): at most 512 Nt bytes of pair rows and 256 Nt of rank-r rows on the routes up to
+        # 15 modes, 64 MiB for the plan's constants; on the wide rank-r route (more modes) 4 (Np + 2 RQ) Nt bytes
+        # (pair rows / C, Y', Y; RQ = the rank G (2 G - 1) rounded up to 16) and 256 MiB for the constants and
+        # the GEMM library's workspace
         groups, nt = cls
         N = synth.n_modes_for_groups(groups)
         c = 16 if self.precision == "fp64" else 8
         rows = self.slots * (self.M + 1)
-        return int(self.slots * (3 * self.M + 4) * N * nt * c + rows * (512 + 256) * nt + (64 << 20))
+        fields = self.slots * (3 * self.M + 4) * N * nt * c
+        if N <= 15:
+            return int(fields + rows * (512 + 256) * nt + (64 << 20))
+        Np, rq = N * (N + 1) // 2, -(-groups * (2 * groups - 1) // 16) * 16
+        return int(fields + rows * 4 * (Np + 2 * rq) * nt + (256 << 20))
 
     def _new_engine(self, cls):
         import torch

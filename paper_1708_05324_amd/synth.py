@@ -261,6 +261,14 @@ def config3(dz: float | None = None) -> Workload:
                          self_steepening=1, M=10, L=1.0, dz=dz, name="grin15_raman_nt16384")
 
 
+def wide_workload(nt: int = 2 ** 15) -> Workload:
+    """55 modes (groups 0-9), Kerr+Raman+shock, 200 fs Gaussian of 100 nJ over the
+    modes, dt = 2.441 fs (Nt = 2^15: an 80 ps window), M = 10, dz by the rule:
+    the largest request shape of the serving stream."""
+    return grin_workload(9, 10, nt, DT_FINE, "gaussian", 200e-15, energy=100e-9, fR=0.18,
+                         self_steepening=1, M=10, L=1.0, name=f"grin55_raman_nt{nt}")
+
+
 def fig3_workload() -> Workload:
     """10 GRIN modes (groups 0-3), Nt = 2^14 over 40 ps, Kerr + Raman + shock, 200 fs
     Gaussian of 100 nJ over the modes, dz = z_NL / 200 (the ratio the timing
@@ -321,7 +329,7 @@ class Request:
     chirp: float
 
 
-def request_stream(seed: int = 5, count: int = 200, rate: float = 200.0, max_groups: int = 5,
+def request_stream(seed: int = 5, count: int = 200, rate: float = 200.0, max_groups: int = 10,
                    length_scale: float = 0.01) -> list[Request]:
     """A seeded Poisson request stream of GRIN propagations: exponential gaps of
     mean 1/rate, then per request (draw order) Hermite-Gauss groups uniform in

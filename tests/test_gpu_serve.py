@@ -22,11 +22,14 @@ def torch_gpu():
     return torch
 
 
-@pytest.mark.parametrize("tight", [False, True])
-def test_served_results_equal_alone(torch_gpu, tight):
+@pytest.mark.parametrize("tight,max_groups,length_scale", [(False, 3, 0.002), (True, 3, 0.002), (False, 7, 5e-4)],
+                         ids=["room", "tight", "to_28_modes"])
+def test_served_results_equal_alone(torch_gpu, tight, max_groups, length_scale):
+    """The third stream reaches 28 modes: classes of 21 and 28 modes run on the
+    wide rank-r route beside classes of the other routes."""
     from paper_1708_05324_amd import gmmpa, serve
     torch = torch_gpu
-    reqs = synth.request_stream(seed=9, count=10, rate=3000.0, max_groups=3, length_scale=0.002)
+    reqs = synth.request_stream(seed=9, count=10, rate=3000.0, max_groups=max_groups, length_scale=length_scale)
     srv = serve.Server(precision="bf16x3", slots=2, keep_fields=True)
     srv.prepare(reqs)
     if tight:   # room for the largest single batch only
