@@ -247,11 +247,15 @@ int gmm_nonlinear_noalloc(gmm_plan plan, const void* At, int count, void* out);
  * timing the candidates on the plan's own buffers, `count` sub-step rows per
  * launch (M + 1 for gmm_propagate, slots (M + 1) for a batch); the fastest is
  * kept for every later call on the plan (propagate, batches, gmm_nonlinear).
- *   FP32 rank-r route: column-owner kernel at 1 or 2 blocks per CU, or the
- *   row-register kernel at 1 to 4 blocks per CU (these two kernels sum in a
- *   different order, so their results differ by rounding);
+ *   FP32 rank-r route: column-owner kernel on 64-column tiles at 1 or 2
+ *   blocks per CU, the row-register kernel at 1 to 4 blocks per CU, or the
+ *   column-owner kernel on 48-column tiles at 1 or 2 blocks per CU (the two
+ *   kernels sum in a different order, so their results differ by rounding);
  *   FP32 packed route: the row-register kernel at 1 to 4 blocks per CU;
- *   BF16X3 rank-r route: the column-owner kernel at 1 or 2 blocks per CU.
+ *   BF16X3 rank-r route: the column-owner kernel on 64- or 48-column tiles at
+ *   1 or 2 blocks per CU.
+ * Until then a plan uses, on the rank-r route, the 48-column column-owner
+ * kernel in BF16X3 and the row-register kernel at 3 blocks per CU in FP32.
  * Other routes: GMM_ERR_UNSUPPORTED.  Allocates the plan's workspace for
  * `count` rows, overwrites it and synchronises the plan's stream.
  *   n_candidates : receives the number of candidates (may be NULL).

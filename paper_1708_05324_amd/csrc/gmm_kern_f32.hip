@@ -57,19 +57,16 @@ hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* S
   return hipErrorInvalidValue;
 }
 
-template <int RPAD, bool BF16>
+template <int RPAD, bool BF16, int CB>
 static int contract_cols_blocks() {
   static int blocks = 0;
   if (blocks == 0) {
     constexpr size_t lds = ColShape<RPAD, BF16>::lds_bytes();
-    if (lds > 65536 && hipFuncSetAttribute((const void*)k_contract_cols<RPAD, BF16>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    const void* fn = (const void*)k_contract_cols<RPAD, BF16, CB>;
+    if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return 0;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_cols<RPAD, BF16>, 256, lds) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     blocks = per_cu * device_cus();
   }
   return blocks;
@@ -77,22 +74,26 @@ static int contract_cols_blocks() {
 
 hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
                                 cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
-                                hipStream_t s, int blocks_per_cu) {
-  const int ntiles = count * (Nt / 64);
-#define GMM_COL_CASE(RP, BF)                                                                                  \
-  if (rpad == RP && bf16 == BF) {                                                                             \
-    int cap = contract_cols_blocks<RP, BF>();                                                                \
-    if (cap < 1) return hipErrorInvalidConfiguration;                                                        \
-    if (blocks_per_cu > 0) cap = std::min(cap, blocks_per_cu * device_cus());                                \
-    const int nb = std::min((ntiles + 3) / 4, cap);                                                          \
-    hipLaunchKernelGGL((k_contract_cols<RP, BF>), dim3(nb), dim3(256), (ColShape<RP, BF>::lds_bytes()), s, Ua, \
-                       Ub, Ya, Yb, A_NL, N, kv, Nt, ntiles, ctrl);                                           \
-    return hipGetLastError();                                                                                 \
+                                hipStream_t s, int blocks_per_cu, int col_blocks) {
+#define GMM_COL_CASE(RP, BF, CB)                                                                               \
+  if (rpad == RP && bf16 == BF && col_blocks == CB) {                                                          \
+    const int ntiles = count * ((Nt + 16 * CB - 1) / (16 * CB));                                               \
+    int cap = contract_cols_blocks<RP, BF, CB>();                                                              \
+    if (cap < 1) return hipErrorInvalidConfiguration;                                                          \
+    if (blocks_per_cu > 0) cap = std::min(cap, blocks_per_cu * device_cus());                                  \
+    const int nb = std::min((ntiles + 3) / 4, cap);                                                            \
+    hipLaunchKernelGGL((k_contract_cols<RP, BF, CB>), dim3(nb), dim3(256), (ColShape<RP, BF>::lds_bytes()), s, \
+                       Ua, Ub, Ya, Yb, A_NL, N, kv, Nt, ntiles, ctrl);                                         \
+    return hipGetLastError();                                                                                  \
   }
-  GMM_COL_CASE(64, true)
-  GMM_COL_CASE(128, true)
-  GMM_COL_CASE(64, false)
-  GMM_COL_CASE(128, false)
+  GMM_COL_CASE(64, true, 4)
+  GMM_COL_CASE(128, true, 4)
+  GMM_COL_CASE(64, false, 4)
+  GMM_COL_CASE(128, false, 4)
+  GMM_COL_CASE(64, true, 3)
+  GMM_COL_CASE(128, true, 3)
+  GMM_COL_CASE(64, false, 3)
+  GMM_COL_CASE(128, false, 3)
 #undef GMM_COL_CASE
   return hipErrorInvalidValue;
 }

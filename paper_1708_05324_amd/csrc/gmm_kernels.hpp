@@ -758,10 +758,15 @@ struct ColShape {
   static constexpr size_t lds_bytes() { return u_bytes() + (size_t)4 * 64 * SLAB * 4; }
 };
 
-template <int RPAD, bool BF16>
+// CB column blocks of 16 per tile: 4 (64 columns, one per lane) or 3 (48 columns: lanes 48..63 fold
+// nothing; a launch of M + 1 sub-steps of 2^14 samples then fills two rounds of the persistent grid
+// instead of one and a third).  The last tile of a sub-step is cut at Nt.
+template <int RPAD, bool BF16, int CB = 4>
 __global__ __launch_bounds__(256, 2) void k_contract_cols(
     const void* __restrict__ Ua, const void* __restrict__ Ub, const void* __restrict__ Ya,
     const void* __restrict__ Yb, cplx<float>* A_NL, int N, int kv, int Nt, int ntiles, const Ctrl* ctrl) {
+  static_assert(CB == 3 || CB == 4, "tiles of 48 or 64 columns");
+  constexpr int TW = 16 * CB;
   using CS = ColShape<RPAD, BF16>;
   constexpr int LMAX = CS::LMAX, SLAB = CS::SLAB, K = CS::K;
   if (skip_iteration(ctrl)) return;
@@ -784,15 +789,16 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
     for (int i = tid; i < K * RPAD; i += 256) sU[(i / RPAD) * (RPAD + 16) + i % RPAD] = ut[i];
   }
   __syncthreads();
-  const int tiles_per_j = Nt / 64;
+  const int tiles_per_j = (Nt + TW - 1) / TW;
   for (int tile_v = blockIdx.x * 4 + wave; tile_v < ntiles; tile_v += gridDim.x * 4) {
     // wave-uniform tile: row bases stay in scalar registers, one lane offset in a vector register
     const int tile = __builtin_amdgcn_readfirstlane(tile_v);
-    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * 64;
+    const int jj = tile / tiles_per_j, t0 = (tile - jj * tiles_per_j) * TW;
+    const int ncol = min(TW, Nt - t0);  // columns of this tile
     cplx<float>* Aj = A_NL + (size_t)jj * N * Nt + t0;
     // operand B (Y') of the whole tile, straight from HBM
-    bf16x8 yh[BF16 ? 4 : 1][2], yl[BF16 ? 4 : 1][2];
-    float yf[BF16 ? 1 : 4][BF16 ? 1 : 16];
+    bf16x8 yh[BF16 ? CB : 1][2], yl[BF16 ? CB : 1][2];
+    float yf[BF16 ? 1 : CB][BF16 ? 1 : 16];
     if constexpr (BF16) {
       // word (i, t) of a plane holds rows 2i, 2i + 1: the eight rows 32 ks + 8 lk .. + 7 are words 16 ks + 4 lk + e;
       // words at or beyond the kv valid rows are zero and are not read
@@ -800,16 +806,17 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
       const uint32_t* pl = reinterpret_cast<const uint32_t*>(Yb) + (size_t)jj * 32 * Nt + t0 + lr;
       const int kw = (kv + 1) >> 1;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
           uint32_t wh[4], wl[4];
+          const bool colok = cb * 16 + lr < ncol;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int word = 16 * ks + 4 * lk + e;
             const size_t o = (size_t)word * Nt + cb * 16;
-            wh[e] = word < kw ? ph[o] : 0u;
-            wl[e] = word < kw ? pl[o] : 0u;
+            wh[e] = word < kw && colok ? ph[o] : 0u;
+            wl[e] = word < kw && colok ? pl[o] : 0u;
           }
           yh[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wh[0], wh[1], wh[2], wh[3]});
           yl[cb][ks] = __builtin_bit_cast(bf16x8, uint4{wl[0], wl[1], wl[2], wl[3]});
@@ -820,22 +827,23 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
       for (int ks = 0; ks < 16; ++ks) {
         const int k = min(4 * ks + lk, kv - 1);
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) yf[cb][ks] = py[(size_t)k * Nt + cb * 16];
+        for (int cb = 0; cb < CB; ++cb) yf[cb][ks] = cb * 16 + lr < ncol ? py[(size_t)k * Nt + cb * 16] : 0.f;
       }
     }
     const unsigned col = lane;  // 32-bit lane offset on a wave-uniform row base
+    const bool mine = (int)lane < ncol;
     cplx<float> a[LMAX], nl[LMAX];
 #pragma unroll
     for (int l = 0; l < LMAX; ++l) {
-      a[l] = l < N ? sgpr_ptr(Aj + (size_t)l * Nt)[col] : cplx<float>{0.f, 0.f};
+      a[l] = l < N && mine ? sgpr_ptr(Aj + (size_t)l * Nt)[col] : cplx<float>{0.f, 0.f};
       nl[l] = cplx<float>{0.f, 0.f};
     }
     static_for<0, CS::GROUPS>([&](auto gc) {
       constexpr int G = decltype(gc)::value;  // rows 16 G .. 16 G + 15
       if constexpr (16 * G < CS::NP_MAX) {
-        floatx4 acc[4];
+        floatx4 acc[CB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
         if constexpr (BF16) {
           const uint4* sU = reinterpret_cast<const uint4*>(smem_raw);
 #pragma unroll
@@ -844,7 +852,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
             const bf16x8 uh = __builtin_bit_cast(bf16x8, sU[r * 9 + 4 * ks + lk]);
             const bf16x8 ul = __builtin_bit_cast(bf16x8, sU[(RPAD + r) * 9 + 4 * ks + lk]);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < CB; ++cb) {
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yh[cb][ks], acc[cb], 0, 0, 0);
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yl[cb][ks], acc[cb], 0, 0, 0);
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul, yh[cb][ks], acc[cb], 0, 0, 0);
@@ -856,13 +864,14 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
           for (int ks = 0; ks < 16; ++ks) {
             const float u = sU[(4 * ks + lk) * (RPAD + 16) + 16 * G + lr];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < CB; ++cb)
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(u, yf[cb][ks], acc[cb], 0, 0, 0);
           }
         }
-        // accumulator register i of lane (lr, lk) holds row 4 lk + i of column lr
+        // accumulator register i of lane (lr, lk) holds row 4 lk + i of column lr (slab rows of the
+        // columns beyond CB blocks are not written; those lanes fold nothing that is stored)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
           *reinterpret_cast<floatx4*>(slab + (cb * 16 + lr) * SLAB + 4 * lk) = acc[cb];
         __builtin_amdgcn_wave_barrier();
         static_for<0, 4>([&](auto mc) {
@@ -887,7 +896,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
     });
 #pragma unroll
     for (int p = 0; p < LMAX; ++p)
-      if (p < N) sgpr_ptr(Aj + (size_t)p * Nt)[col] = nl[p];
+      if (p < N && mine) sgpr_ptr(Aj + (size_t)p * Nt)[col] = nl[p];
   }
 }
 

@@ -160,7 +160,8 @@ struct gmm_plan_s {
   // rank-r route (Raman on, low-rank packed matrix): S^ = U V
   bool factored = false;
   int rank = 0, rq = 0, kp = 0;  // r, r rounded up to 16, Np rounded up to 64
-  // contraction launch chosen by gmm_plan_autotune: kernel (rank-r FP32 route: 0 column-owner, 1 row-register)
+  // contraction launch chosen by gmm_plan_autotune: kernel (rank-r FP32 route: 0 column-owner, 1 row-register,
+  // 2 column-owner on 48-column tiles; rank-r BF16X3 route: 0 column-owner, 1 the same on 48-column tiles)
   // and blocks per CU of the persistent grid (0: as many as fit)
   int tune_kernel = 0, tune_bpc = 0;
   void* VT = nullptr;      // [kp][rq] V transposed, field precision
@@ -342,8 +343,9 @@ EvalWs plan_ws(const gmm_plan_s* P) {
 }
 
 // Launch candidates of the contraction that gmm_plan_autotune times, in its
-// numbering: kernel (rank-r FP32 route: 0 column-owner, 1 row-register) and
-// blocks per CU of the persistent grid.
+// numbering: kernel (rank-r FP32 route: 0 column-owner, 1 row-register, 2
+// column-owner on 48-column tiles; rank-r BF16X3 route: 0 column-owner, 1 the
+// same on 48-column tiles) and blocks per CU of the persistent grid.
 struct ContractCand {
   int kernel, bpc;
 };
@@ -354,8 +356,10 @@ std::vector<ContractCand> contraction_candidates(const gmm_plan_s* P) {
     for (int b : {1, 2}) c.push_back({0, b});
     if (P->rt <= 2)
       for (int b : {1, 2, 3, 4}) c.push_back({1, b});
+    for (int b : {1, 2}) c.push_back({2, b});
   } else if (P->factored) {
     for (int b : {1, 2}) c.push_back({0, b});
+    for (int b : {1, 2}) c.push_back({1, b});
   } else if (!P->bf16 && P->rt <= 2) {
     for (int b : {1, 2, 3, 4}) c.push_back({0, b});
   }
@@ -466,7 +470,7 @@ struct Runner {
           if (doB)
             GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, true, P->Uhi, P->Ulo, bhi, blo, W,
                                                                      P->N, R, P->nt, count, ctrl, P->stream,
-                                                                     P->tune_bpc));
+                                                                     P->tune_bpc, P->tune_kernel == 1 ? 3 : 4));
         }
       }
       if (!P->bf16) {
@@ -486,7 +490,7 @@ struct Runner {
           else if (doB)
             GMM_LAUNCH(P, GMM_PROF_CONTRACT, gmm::launch_contract_cols(P->rpad, false, P->UT, nullptr, ws.Bp, nullptr,
                                                                      W, P->N, P->rq, P->nt, count, ctrl, P->stream,
-                                                                     P->tune_bpc));
+                                                                     P->tune_bpc, P->tune_kernel == 2 ? 3 : 4));
         } else if (doB) {
           GMM_LAUNCH(P, GMM_PROF_CONTRACT, Launch<T>::contract(P->rt, 64, (const T*)P->UT, (const T*)ws.Bp, W,
                                                                P->pidx, P->N, P->rq, P->nt, count, ctrl, P->stream));
@@ -1168,6 +1172,12 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
   P->rank = r;
   P->rq = rq;
   P->kp = kp;
+  // default contraction launch (gmm_plan_autotune may pick another): BF16X3 the column-owner kernel on
+  // 48-column tiles (M + 1 = 11 sub-steps of 2^14 samples fill two rounds of the persistent grid), FP32 the
+  // row-register kernel at 3 blocks per CU (the fastest of the candidates on the 15-mode 2^14 workload)
+  P->tune_kernel = 1;
+  P->tune_bpc = P->bf16 ? 0 : (P->rt <= 2 ? 3 : 0);
+  if (!P->bf16 && P->rt > 2) P->tune_kernel = 0;
   return GMM_OK;
 }
 
