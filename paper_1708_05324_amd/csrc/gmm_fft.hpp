@@ -4,9 +4,11 @@
 // (FP32 rows of 2^10 and more; 16 otherwise) in registers, does a radix-R butterfly per pass entirely in
 // registers, and the passes exchange data through LDS in Stockham (self-
 // sorting) order, so no bit-reversal pass is ever needed.  An FP32 2^14 row
-// takes three passes [32, 16, 32] and two LDS exchanges.  Real and imaginary
-// parts travel through LDS separately (N scalars + 1/16 padding), which keeps
-// an FP64 2^14 row inside the 160 KB LDS and lets two FP32 rows share a CU.
+// takes three passes [32, 16, 32] and two LDS exchanges.  An exchange moves
+// the real and then the imaginary parts through N scalars of LDS (+ 1/16
+// padding), which keeps an FP64 2^14 row inside the 160 KB LDS and lets two
+// FP32 rows share a CU; a WIDE FP32 row (one per CU) moves N complex values
+// in one round, one LDS access per point and direction.
 //
 // The pass schedule is [R, rem, R, ..., R]: first and last passes both have
 // radix R, so the register of the i-th point is i*THREADS + tid both on entry
@@ -21,10 +23,15 @@
 
 namespace gmm {
 
-template <int LOGN_, int ELEM_BYTES, int MAX_LOGR = 5>
+// WIDE_: the row may take the LDS of a whole CU (one block per CU): an FP32 row
+// of up to 2^14 points then goes through LDS as N complex values in one round
+// (2 N scalars + 1/16 padding, 139 KB at 2^14) instead of its real and
+// imaginary parts one after the other.
+template <int LOGN_, int ELEM_BYTES, int MAX_LOGR = 5, bool WIDE_ = false>
 struct FftShape {
   static constexpr int LOGN = LOGN_;
   static constexpr int N = 1 << LOGN;
+  static constexpr bool WIDE = WIDE_ && ELEM_BYTES == 4 && LOGN <= 14;
   // 32 points per thread for FP32 rows of 2^10 and more; 16 for FP64 rows
   // (32 complex doubles would need 128 VGPRs for the data alone).
   static constexpr int LOGR = (ELEM_BYTES == 4 && LOGN >= 10 && MAX_LOGR >= 5) ? 5 : 4;
@@ -33,7 +40,7 @@ struct FftShape {
   static constexpr int NFULL = LOGN / LOGR;
   static constexpr int REM = LOGN % LOGR;
   static constexpr int NPASS = NFULL + (REM ? 1 : 0);
-  static constexpr int LDS_ELEMS = N + (N >> 4);  // one padding slot per 16
+  static constexpr int LDS_ELEMS = (WIDE ? 2 : 1) * (N + (N >> 4));  // one padding slot per 16 points
   static constexpr int logp(int i) { return (i == 1 && REM) ? REM : LOGR; }
   static constexpr int log_stride(int i) {
     int s = 0;
@@ -155,9 +162,9 @@ __device__ __forceinline__ void fft_pass_compute(cplx<T> (&v)[S::R], const PassT
   }
 }
 
-// LDS padding of the exchange after pass I: one slot every 2^s elements with
+// LDS padding of the exchange after pass I: one slot every 2^s points with
 // s = max(log2 P_I, 4), so the stride-P (or run-of-Ns) writes of the pass fall
-// on distinct banks; never more than S::N / 16 extra slots.
+// on distinct banks; never more than N / 16 extra slots.
 template <class S, int I>
 __device__ __forceinline__ int lds_pad_x(int i) {
   constexpr int LP = S::logp(I);
@@ -165,7 +172,33 @@ __device__ __forceinline__ int lds_pad_x(int i) {
   return i + (i >> SH);
 }
 
-// Write pass I's outputs to LDS (one component), read pass I+1's inputs.
+// Exchange after pass I of a WIDE row: every point of pass I's output is
+// written to LDS as one complex value, then pass I+1's inputs are read.
+template <class S, int I, typename T>
+__device__ __forceinline__ void fft_exchange_wide(cplx<T> (&v)[S::R], T* lds, int tid) {
+  constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
+  constexpr int LNS = S::log_stride(I), NS = 1 << LNS;
+  constexpr int LP2 = S::logp(I + 1), P2 = 1 << LP2, B2 = S::R / P2;
+  cplx<T>* c = reinterpret_cast<cplx<T>*>(lds);
+  __syncthreads();  // the previous exchange has been read
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = tid + b * S::THREADS;
+    const int base = ((j >> LNS) << (LNS + LP)) + (j & (NS - 1));
+#pragma unroll
+    for (int q = 0; q < P; ++q) c[lds_pad_x<S, I>(base + (q << LNS))] = v[b * P + q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < B2; ++b) {
+    const int j = tid + b * S::THREADS;
+#pragma unroll
+    for (int q = 0; q < P2; ++q) v[b * P2 + q] = c[lds_pad_x<S, I>(j + q * (S::N / P2))];
+  }
+}
+
+// Exchange after pass I of other rows: the real and imaginary parts go through
+// LDS one after the other (N scalars each).
 template <class S, int I, typename T, bool IMAG>
 __device__ __forceinline__ void fft_exchange_component(cplx<T> (&v)[S::R], T* lds, int tid) {
   constexpr int LP = S::logp(I), P = 1 << LP, B = S::R / P;
@@ -192,6 +225,16 @@ __device__ __forceinline__ void fft_exchange_component(cplx<T> (&v)[S::R], T* ld
   }
 }
 
+template <class S, int I, typename T>
+__device__ __forceinline__ void fft_exchange(cplx<T> (&v)[S::R], T* lds, int tid) {
+  if constexpr (S::WIDE) {
+    fft_exchange_wide<S, I, T>(v, lds, tid);
+  } else {
+    fft_exchange_component<S, I, T, false>(v, lds, tid);
+    fft_exchange_component<S, I, T, true>(v, lds, tid);
+  }
+}
+
 template <class S, int I, typename T, int SIGN>
 __device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw,
                                            const PassTwiddles<S, I, T, SIGN>& tws) {
@@ -199,14 +242,13 @@ __device__ __forceinline__ void fft_passes(cplx<T> (&v)[S::R], T* lds, int tid, 
   if constexpr (I + 1 < S::NPASS) {
     PassTwiddles<S, I + 1, T, SIGN> next;
     next.load(tid, tw);
-    fft_exchange_component<S, I, T, false>(v, lds, tid);
-    fft_exchange_component<S, I, T, true>(v, lds, tid);
+    fft_exchange<S, I, T>(v, lds, tid);
     fft_passes<S, I + 1, T, SIGN>(v, lds, tid, tw, next);
   }
 }
 
 // Full transform of the row held in v (v[i] = x[tid + i*THREADS]) in place.
-// `lds` must hold S::LDS_ELEMS scalars of type T.  All threads must call it.
+// `lds` must hold S::LDS_ELEMS scalars of type T, 16-byte aligned.  All threads must call it.
 template <class S, typename T, int SIGN>
 __device__ __forceinline__ void block_fft(cplx<T> (&v)[S::R], T* lds, int tid, const cplx<T>* __restrict__ tw) {
   PassTwiddles<S, 0, T, SIGN> first;  // pass 0 has Ns = 1: no twiddles

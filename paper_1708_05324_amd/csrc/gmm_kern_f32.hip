@@ -410,7 +410,7 @@ __global__ __launch_bounds__((FftShape<kOsLogF, 4, 4>::THREADS)) void k_pairs_de
     const cplx<float>* __restrict__ twf, const Ctrl* ctrl) {
   using S = FftShape<kOsLogF, 4, 4>;
   if (skip_iteration(ctrl)) return;
-  __shared__ float lds[S::LDS_ELEMS];
+  __shared__ __align__(16) float lds[S::LDS_ELEMS];
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * Np * count);
   if (w < 0) return;
   const int tid = threadIdx.x;

@@ -57,10 +57,10 @@ __device__ __forceinline__ double disp_phase(const double* __restrict__ coef, in
 // ---------------------------------------------------------------------------
 // Plain row transform: out = scale * FFT_SIGN(in), one row per block.
 template <typename T, int LOGN, int SIGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_fft_rows(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), 5, true>::THREADS)) void k_fft_rows(
     const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, T scale, const cplx<T>* __restrict__ tw) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
-  __shared__ T lds[S::LDS_ELEMS];
+  using S = FftShape<LOGN, (int)sizeof(T), 5, true>;
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const size_t row = (size_t)blockIdx.x * S::N;
   cplx<T> v[S::R];
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_mode_mix(const cplx<T>* src, long src_j
 template <typename T, int LOGN>
 __device__ __forceinline__ void phase_to_time_row(const cplx<T>* src, const cplx<T>* __restrict__ ph,
                                                   cplx<T>* dst, T* lds, int tid, const cplx<T>* __restrict__ tw) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
+  using S = FftShape<LOGN, (int)sizeof(T), 5, true>;
   cplx<T> v[S::R];
   if (ph != nullptr) {
 #pragma unroll
@@ -222,12 +222,12 @@ __device__ __forceinline__ void phase_to_time_row(const cplx<T>* src, const cplx
 }
 
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), 5, true>::THREADS)) void k_phase_to_time(
     const cplx<T>* psi, long psi_jrows, cplx<T>* A, const cplx<T>* __restrict__ E, int j0,
     const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
+  using S = FftShape<LOGN, (int)sizeof(T), 5, true>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
   const cplx<T>* src = psi + ((size_t)jj * psi_jrows + p) * S::N;
   const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
     const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
+  __shared__ __align__(16) T lds[RAMAN ? S::LDS_ELEMS : 1];
   const int PB = (Np + 1) / 2;  // pair blocks per sub-step; 1-D grid of 8 G blocks
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
   if (w < 0) return;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__((FftShape<LOGN, 4>::THREADS)) void k_pairs_bf16(
     const cplx<float>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, 4>;
   if (skip_iteration(ctrl)) return;
-  __shared__ float lds[RAMAN ? S::LDS_ELEMS : 1];
+  __shared__ __align__(16) float lds[RAMAN ? S::LDS_ELEMS : 1];
   const int PB = (Np + 1) / 2;  // pair blocks per sub-step; 1-D grid of 8 G blocks
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
   if (w < 0) return;
@@ -1122,7 +1122,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF1
     int RQ, int count, int KW, const cplx<T>* __restrict__ Gs, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T), kConvLogR<LOGN, BF16OUT>>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int PB = (R + 1) / 2;
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, PB * count);
   if (w < 0) return;
@@ -1179,7 +1179,7 @@ __global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), si
     const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
   using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int PB = (R + 1) / 2;
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * PB * count);
   if (w < 0) return;
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__((FftShape<kOsLogF, (int)sizeof(T), 4>::THREADS), si
     const cplx<T>* __restrict__ Gf, const cplx<T>* __restrict__ twf, const Ctrl* ctrl) {
   using S = FftShape<kOsLogF, (int)sizeof(T), 4>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int PB = (Np + 1) / 2;
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, nseg * PB * count);
   if (w < 0) return;
@@ -1303,7 +1303,7 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
     int KD, const cplx<T>* __restrict__ Hr, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
   using S = FftShape<LOGN, (int)sizeof(T)>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[RAMAN ? S::LDS_ELEMS : 1];
+  __shared__ __align__(16) T lds[RAMAN ? S::LDS_ELEMS : 1];
   const int w = xcd_local_index(blockIdx.x, gridDim.x >> 3, Np * count);
   if (w < 0) return;
   const int tid = threadIdx.x, jj = w / Np, Q = w - jj * Np;
@@ -1415,7 +1415,7 @@ template <typename T, int LOGN>
 __device__ __forceinline__ void spectral_out_row(const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ ph,
                                                  double domega, double gscale, double inv_omega0, int shock, T* lds,
                                                  int tid, const cplx<T>* __restrict__ tw) {
-  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>;
   cplx<T> v[S::R];
 #pragma unroll
   for (int i = 0; i < S::R; ++i) v[i] = in[tid + i * S::THREADS];
@@ -1434,12 +1434,12 @@ __device__ __forceinline__ void spectral_out_row(const cplx<T>* in, cplx<T>* out
 }
 
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>::THREADS)) void k_spectral_out(
     const cplx<T>* in, cplx<T>* out, const cplx<T>* __restrict__ E, int j0, double domega, double gscale,
     double inv_omega0, int shock, const cplx<T>* __restrict__ tw, const Ctrl* ctrl) {
-  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>;
   if (skip_iteration(ctrl)) return;
-  __shared__ T lds[S::LDS_ELEMS];
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, jj = blockIdx.y, N = gridDim.x;
   const size_t row = ((size_t)jj * N + p) * S::N;
   const cplx<T>* ph = E != nullptr ? E + ((size_t)(j0 + jj) * N + p) * S::N : nullptr;
@@ -1595,11 +1595,11 @@ __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, 
 
 // lab = 1: lab-frame storage (rows from stored iterates take no factor; spectral outputs keep none).
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_phase_to_time_b(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), 5, true>::THREADS)) void k_phase_to_time_b(
     const BatchRow* __restrict__ rows, const cplx<T>* psi0, const cplx<T>* psi, const cplx<T>* __restrict__ E,
     cplx<T>* A, int M, const cplx<T>* __restrict__ tw, int lab) {
-  using S = FftShape<LOGN, (int)sizeof(T)>;
-  __shared__ T lds[S::LDS_ELEMS];
+  using S = FftShape<LOGN, (int)sizeof(T), 5, true>;
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
   const BatchRow d = rows[r];
   const size_t nn = (size_t)N * S::N;
@@ -1610,11 +1610,11 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T)>::THREADS)) void k_p
 }
 
 template <typename T, int LOGN>
-__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>::THREADS)) void k_spectral_out_b(
+__global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>::THREADS)) void k_spectral_out_b(
     const BatchRow* __restrict__ rows, cplx<T>* W, const cplx<T>* __restrict__ E, int M, double domega,
     double gscale, double inv_omega0, int shock, const cplx<T>* __restrict__ tw, int lab) {
-  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
-  __shared__ T lds[S::LDS_ELEMS];
+  using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>;
+  __shared__ __align__(16) T lds[S::LDS_ELEMS];
   const int p = blockIdx.x, r = blockIdx.y, N = gridDim.x;
   const BatchRow d = rows[r];
   const size_t nn = (size_t)N * S::N;

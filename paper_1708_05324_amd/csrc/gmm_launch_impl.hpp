@@ -245,7 +245,7 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
                                    int j0, double domega, double gscale, double inv_omega0, int shock,
                                    const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s) {
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>;
     hipLaunchKernelGGL((k_spectral_out<T, LOGN>), dim3(N, count), dim3(S::THREADS), 0, s, in, out, E, j0, domega,
                        gscale, inv_omega0, shock, tw, ctrl);
   });
@@ -365,7 +365,7 @@ hipError_t Launch<T>::spectral_out_b(int logn, const BatchRow* rows, cplx<T>* W,
                                      const cplx<T>* tw, int lab, hipStream_t s) {
   if (R < 1) return hipSuccess;
   GMM_LOGN_SWITCH(logn, {
-    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>>;
+    using S = FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>, true>;
     hipLaunchKernelGGL((k_spectral_out_b<T, LOGN>), dim3(N, R), dim3(S::THREADS), 0, s, rows, W, E, M, domega, gscale,
                        inv_omega0, shock, tw, lab);
   });
