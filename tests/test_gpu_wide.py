@@ -140,3 +140,36 @@ def test_wide_route_limits(torch_gpu):
     with pytest.raises(gmmpa.GmmError) as e:
         gmmpa.plan_from_workload(w6, precision="fp32", factor_policy=3)
     assert e.value.code == gmmpa.GMM_ERR_TENSOR
+
+
+def test_wide_route_at_the_largest_served_shape(torch_gpu):
+    """55 modes, Nt = 2^15 (the largest request of the serving stream), two
+    large steps in tolerance mode.  The oracle cannot run this size, so the
+    check is by properties: the photon number sum_k |A_k|^2 / (w0 + w_k), which
+    the GMMNLSE with Raman and self-steepening conserves, is kept to 1e-5 (the
+    trapezoid's truncation over 20 steps of z_NL / 200 and the FP32 transforms
+    are well below that), and the BF16X3 field agrees with the FP32 plan's to
+    the BF16-split bound of 1e-3 (operator parity at this mode count is in
+    test_wide_route_operator_matches_oracle)."""
+    from paper_1708_05324_amd import gmmpa
+    torch = torch_gpu
+    w = synth.wide_workload(2 ** 15)
+    L = 2 * w.M * w.dz
+    out = {}
+    for prec, tol in (("bf16x3", 3e-5), ("fp32", 1e-6)):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
+        assert plan.rank() == 190
+        res = plan.propagate(to_dev(torch, w.A0), L, w.dz, w.M)
+        st = res.stats
+        drift = abs(st["photons_out"] / st["photons_in"] - 1.0)
+        print(f"[{prec} N=55 nt=32768] photon-number drift {drift:.2e}, iterations {st['iterations']}, "
+              f"plan {plan.device_bytes() / 2 ** 30:.2f} GiB", flush=True)
+        assert st["large_steps"] == 2 and st["nonconverged_steps"] == 0
+        assert drift < 1e-5
+        assert drift < 1e-6   # measured 5e-8: a regression far below the stated bound shows here
+        out[prec] = res.field.cpu().numpy()
+        plan.close()
+    err = relmax(out["bf16x3"], out["fp32"])
+    print(f"[N=55 nt=32768] BF16X3 vs FP32 field {err:.2e}", flush=True)
+    assert err < 1e-3
+    assert err < 1e-5     # measured 5e-7
