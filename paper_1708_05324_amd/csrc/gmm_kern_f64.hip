@@ -5,27 +5,31 @@ template struct gmm::Launch<double>;
 
 namespace gmm {
 
-// Fixed-order reduction of the partial sums and the stopping decision.
+// Fixed-order reduction of the partial sums and the stopping decision: thread
+// t adds partials t, t + 256, ... in order, each wave reduces its 64 sums by a
+// butterfly of lane shuffles (the same pairing every launch: deterministic),
+// and thread 0 adds the four wave sums in wave order after one barrier.
 __device__ __forceinline__ void norm_final_block(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
                                                  double tol, int fixed_iters, int max_iter) {
-  __shared__ double red[2][256];
+  __shared__ double wsum[2][4];
   double d = 0.0, s = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 256) {
     d += partials[2 * b];
     s += partials[2 * b + 1];
   }
-  red[0][threadIdx.x] = d;
-  red[1][threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o);
+    s += __shfl_xor(s, o);
   }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[0][threadIdx.x >> 6] = d;
+    wsum[1][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double dn = red[0][0], sn = red[1][0];
+    const double dn = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+    const double sn = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
     // a non-finite sum means a non-finite field value: report it (eps = NaN), never as converged
     const double eps = (!isfinite(dn) || !isfinite(sn)) ? __builtin_nan("") : sn > 0.0 ? sqrt(dn / sn) : 0.0;
     const int it = ctrl->iters + 1;
