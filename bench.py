@@ -396,6 +396,56 @@ def bench_serve(args) -> dict:
             "at_offered_rate": first, "at_0.7x_capacity": dict(second, offered_rate_per_s=round(0.7 * capacity, 3))}
 
 
+def bench_configs() -> dict:
+    """The two small configurations run as stated.  Config 1 (3 modes, Kerr only,
+    dz = 1 mm) over its full 0.5 m in FP64: the energy invariant, and the field
+    against the oracle's RK4IP over the same 0.5 m at the same step.  Config 2
+    (6 modes, Raman, 1 m): once at its stated dz = 2 mm (M dz gamma P0 = 3.2, far
+    outside the regime L << z_NL the method needs) with the status the library
+    returns, then over the full 1 m at the step rule, FP64 and FP32."""
+    import numpy as np
+    import torch
+    from oracle import gmmnlse as O
+    from paper_1708_05324_amd import gmmpa, synth
+
+    def run(w, prec, L, dz, M, tol):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
+        dtype = torch.complex128 if prec == "fp64" else torch.complex64
+        A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            res = plan.propagate(A, L, dz, M)
+            rc, st, field = res.status, res.stats, res.field.cpu().numpy()
+        except gmmpa.GmmError as e:
+            rc, st, field = e.code, None, None
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        plan.close()
+        out = {"status": {0: "ok", 1: "not converged (max_iter reached in some large steps)",
+                          -6: "diverged (non-finite relative change)"}.get(rc, str(rc)), "seconds": round(sec, 3)}
+        if st:
+            out.update({"large_steps": st["large_steps"], "small_steps": st["small_steps"],
+                        "nonconverged_steps": st["nonconverged_steps"], "iterations": st["iterations"],
+                        "small_steps_per_s": round(st["small_steps"] / sec, 1),
+                        "energy_rel_change": float(st["energy_out"] / st["energy_in"] - 1.0),
+                        "photon_number_rel_change": float(st["photons_out"] / st["photons_in"] - 1.0)})
+        return out, field
+
+    out = {"metric": "configurations 1 and 2 as stated", "unit": "-"}
+    w1 = synth.config1()
+    r1, f1 = run(w1, "fp64", w1.L, w1.dz, w1.M, TOL["fp64"])
+    ref = O.rk4ip_propagate(w1.A0, O.model_from_workload(w1), w1.L, w1.dz)
+    r1["field_vs_oracle_rk4ip_same_dz"] = float(np.max(np.abs(f1 - ref)) / np.max(np.abs(ref)))
+    out["config1_fp64_full_0.5m"] = dict(r1, dz_m=w1.dz, L_m=w1.L, M=w1.M)
+    w2s = synth.config2(dz=2e-3)
+    out["config2_stated_dz_2mm"] = {p: run(w2s, p, w2s.L, w2s.dz, w2s.M, TOL[p])[0] for p in ("fp64", "fp32")}
+    w2 = synth.config2()
+    out["config2_rule_dz_full_1m"] = {p: dict(run(w2, p, w2.L, w2.dz, w2.M, TOL[p])[0], dz_um=round(w2.dz * 1e6, 3))
+                                      for p in ("fp64", "fp32")}
+    return out
+
+
 def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
     """The FP64 oracle on the host: large steps (M small steps each) of the same
     workload from its launch field, until at least min_seconds of work.  The
@@ -450,6 +500,10 @@ def main():
     ap.add_argument("--wide", action="store_true",
                     help="only time the wide rank-r route on 55 modes (ten Hermite-Gauss groups, rank 190) at "
                          "Nt = 2^15 and 2^14 in the chosen precision (tolerance mode), and print its own JSON line")
+    ap.add_argument("--configs", action="store_true",
+                    help="only run configurations 1 and 2 as stated (config 1 over 0.5 m in FP64 against the "
+                         "oracle's RK4IP; config 2 at its stated dz = 2 mm and at the step rule over 1 m) and "
+                         "print their JSON line")
     ap.add_argument("--coupling-exact", action="store_true",
                     help="only time the metric workload with a Hermitian linear coupling matrix placed in the "
                          "linear operator (per-frequency eigenbasis, mode mixing around the transforms)")
@@ -616,6 +670,9 @@ def main():
         return
     if args.serve:
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.configs:
+        print(json.dumps(bench_configs()), flush=True)
         return
     if args.batch:
         print(json.dumps(bench_batch(args.length_scale)), flush=True)
