@@ -446,6 +446,49 @@ def bench_configs() -> dict:
     return out
 
 
+def bench_full_length() -> dict:
+    """The metric workload over its full 1 m (about 110 000 small steps) in FP64
+    (tol 1e-12), FP32 (1e-6) and BF16X3 (3e-5): each precision's field error at
+    1 m against the FP64 run (whose first 2 mm match the oracle to 1.3e-14), and
+    the conditioning at 1 m: the FP64 run again from the launch field perturbed
+    by 1e-12 relative (seeded), kappa = (change at 1 m) / 1e-12."""
+    import numpy as np
+    import torch
+    from paper_1708_05324_amd import gmmpa, synth
+    w = synth.config3()
+
+    def run(prec, A0):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30)
+        dtype = torch.complex128 if prec == "fp64" else torch.complex64
+        A = torch.from_numpy(A0).to(device="cuda", dtype=dtype)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.propagate(A, w.L, w.dz, w.M)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        plan.close()
+        st = res.stats
+        return res.field.cpu().numpy().astype(np.complex128), {
+            "seconds": round(sec, 2), "small_steps": st["small_steps"], "small_steps_per_s": round(st["small_steps"] / sec, 1),
+            "iterations_per_large_step": round(st["iterations"] / st["large_steps"], 3),
+            "nonconverged_steps": st["nonconverged_steps"],
+            "photon_number_rel_change": float(st["photons_out"] / st["photons_in"] - 1.0)}
+
+    ref, r64 = run("fp64", w.A0)
+    out = {"metric": "metric workload over the full 1 m: field error per precision against FP64", "unit": "-",
+           "config": {"workload": "grin15_raman_nt16384", "L_m": w.L, "dz_um": round(w.dz * 1e6, 4), "M": w.M},
+           "fp64": r64}
+    peak = float(np.max(np.abs(ref)))
+    for prec in ("fp32", "bf16x3"):
+        f, r = run(prec, w.A0)
+        r["field_error_vs_fp64"] = float(np.max(np.abs(f - ref)) / peak)
+        out[prec] = r
+    eta = np.random.default_rng(synth.SEED_BASE + 7000).standard_normal(w.A0.shape)
+    fp, _ = run("fp64", w.A0 * (1.0 + 1e-12 * eta))
+    out["kappa_1m_fp64"] = float(np.max(np.abs(fp - ref)) / peak / 1e-12)
+    return out
+
+
 def cpu_baseline(w, min_seconds: float = 10.0, max_large_steps: int = 6):
     """The FP64 oracle on the host: large steps (M small steps each) of the same
     workload from its launch field, until at least min_seconds of work.  The
@@ -500,6 +543,9 @@ def main():
     ap.add_argument("--wide", action="store_true",
                     help="only time the wide rank-r route on 55 modes (ten Hermite-Gauss groups, rank 190) at "
                          "Nt = 2^15 and 2^14 in the chosen precision (tolerance mode), and print its own JSON line")
+    ap.add_argument("--full-length", action="store_true",
+                    help="only run the metric workload over its full 1 m in FP64, FP32 and BF16X3 (field errors "
+                         "against FP64, conditioning probe at 1 m) and print their JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="only run configurations 1 and 2 as stated (config 1 over 0.5 m in FP64 against the "
                          "oracle's RK4IP; config 2 at its stated dz = 2 mm and at the step rule over 1 m) and "
@@ -673,6 +719,9 @@ def main():
         return
     if args.configs:
         print(json.dumps(bench_configs()), flush=True)
+        return
+    if args.full_length:
+        print(json.dumps(bench_full_length()), flush=True)
         return
     if args.batch:
         print(json.dumps(bench_batch(args.length_scale)), flush=True)

@@ -34,6 +34,8 @@ struct BatchSlot {
   void* dst;          // close: psi(z0 + m dz) goes here (the slot's psi_0)
   const void* Em;     // close: exp(D_w m dz) row of the slot's table (NULL: lab-frame iterates, a copy)
   const void* E;      // trapezoid with lab-frame storage: the slot's table [M + 1][N][Nt] (NULL: psi frame)
+  const void* Em64;   // trapezoid: exp(D_w M dz) [N][Nt] in FP64 for a full large step of single-precision fields
+                      // (the sub-step that ends the step multiplies in FP64), else NULL
   double* partials;   // [trapz_blocks(N Nt)][2] FP64 partial sums of the norm
   Ctrl* ctrl;         // the slot's control block
   double dz;
@@ -64,6 +66,10 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cplx<double> cwiden(cplx<T> a) { return {(double)a.re, (double)a.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cround(cplx<double> a) { return {(T)a.re, (T)a.im}; }
 
 // exp(i*phase) with the phase first folded into [-pi, pi] in double precision,
 // then evaluated in the field precision T.

@@ -73,15 +73,16 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), 5, true>::THREADS))
 
 // ---------------------------------------------------------------------------
 // Dispersion phase table E[j][p][k] = exp(i (beta_p(w_k) - beta_0) z_j),
-// z_j = j dz, j = 0 .. rows - 1: the FP64 phase is folded into [-pi, pi] and
-// evaluated once per plan and step size; the iterated kernels read it.
+// z_j = j dz, j = j0 .. j0 + rows - 1: the FP64 phase is folded into [-pi, pi]
+// and evaluated once per plan and step size; the iterated kernels read it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_phase_table(cplx<T>* __restrict__ E, const double* __restrict__ coef,
-                                                     int nb, int N, int nt, long total, double dz, double domega) {
+                                                     int nb, int N, int nt, long total, double dz, double domega,
+                                                     int j0) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
   const long row = e / nt;
-  const int k = (int)(e - row * nt), p = (int)(row % N), j = (int)(row / N);
+  const int k = (int)(e - row * nt), p = (int)(row % N), j = j0 + (int)(row / N);
   E[e] = expi_reduced<T>(disp_phase(coef + p * nb, nb, omega_of(k, nt, domega)) * ((double)j * dz));
 }
 
@@ -92,11 +93,11 @@ __global__ __launch_bounds__(256) void k_phase_table(cplx<T>* __restrict__ E, co
 // E[j][q][k] = exp(i lambda_q(w_k) j dz), lam [N][nt] in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_phase_table_lam(cplx<T>* __restrict__ E, const double* __restrict__ lam,
-                                                         int N, int nt, long total, double dz) {
+                                                         int N, int nt, long total, double dz, int j0) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
   const long row = e / nt;
-  const int k = (int)(e - row * nt), q = (int)(row % N), j = (int)(row / N);
+  const int k = (int)(e - row * nt), q = (int)(row % N), j = j0 + (int)(row / N);
   E[e] = expi_reduced<T>(lam[(size_t)q * nt + k] * ((double)j * dz));
 }
 
@@ -1504,11 +1505,17 @@ __device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, co
 //   Nl  : the iteration's spectral outputs: first = 1: rows 0..M (row 0 is I_0);
 //         else rows 1..M of the sub-steps j = 1..M at I + (j - 1) nn, and I_0 kept
 //   psi : [M][N][Nt] stored iterates exp(D z_j) psi_j, row j - 1 = sub-step j
+//   Em64: NULL, or exp(D_w M dz) in FP64 for a single-precision field: the factor
+//         that carries the field from one large step to the next (the others
+//         only shape a step's iterates).  A rounded phase there repeats every
+//         step and adds up over a long fiber (about 1e-7 rad per bin and step),
+//         so the last sub-step takes the FP64 factor and product, rounded once.
 template <typename T>
 __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0,
                                                 const cplx<T>* __restrict__ I, cplx<T>* __restrict__ psi,
                                                 cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
-                                                int first, int M, long nn, T dz, double* __restrict__ partials) {
+                                                const cplx<double>* __restrict__ Em64, int first, int M, long nn,
+                                                T dz, double* __restrict__ partials) {
   __shared__ double red[2][256];
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
@@ -1519,12 +1526,15 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
     const cplx<T> h0 = cscale(i0, T(0.5));
     cplx<T> run = {0, 0};
     for (int j = 0; j < M; ++j) {
-      const cplx<T> ej = E[(size_t)(j + 1) * nn + e];
+      const bool wide = Em64 != nullptr && j == M - 1;
+      const cplx<double> e64 = wide ? Em64[e] : cplx<double>{0.0, 0.0};
+      const cplx<T> ej = wide ? cplx<T>{(T)e64.re, (T)e64.im} : E[(size_t)(j + 1) * nn + e];
       const cplx<T> ij = cmul(I[(size_t)j * nn + e], cplx<T>{ej.re, -ej.im});
       cplx<T> acc = cadd(cadd(h0, run), cscale(ij, T(0.5)));
-      const cplx<T> nw = cmul(cplx<T>{p0.re + dz * acc.re, p0.im + dz * acc.im}, ej);
+      const cplx<T> x = {p0.re + dz * acc.re, p0.im + dz * acc.im};
+      const cplx<T> nw = wide ? cround<T>(cmul(cwiden(x), e64)) : cmul(x, ej);
       run = cadd(run, ij);
-      const cplx<T> old = first ? cmul(p0, ej) : psi[(size_t)j * nn + e];
+      const cplx<T> old = !first ? psi[(size_t)j * nn + e] : wide ? cround<T>(cmul(cwiden(p0), e64)) : cmul(p0, ej);
       const double dr = (double)nw.re - (double)old.re, di = (double)nw.im - (double)old.im;
       d += dr * dr + di * di;
       s += (double)nw.re * nw.re + (double)nw.im * nw.im;
@@ -1550,10 +1560,11 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
 template <typename T>
 __global__ __launch_bounds__(256) void k_trapz_lab(
     const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
-    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E, int first, int M,
-    long nn, T dz, double* __restrict__ partials, const Ctrl* ctrl) {
+    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
+    const cplx<double>* __restrict__ Em64, int first, int M, long nn, T dz, double* __restrict__ partials,
+    const Ctrl* ctrl) {
   if (skip_iteration(ctrl)) return;
-  trapz_lab_block<T>(psi0, I0, I, psi, I0_keep, E, first, M, nn, dz, partials);
+  trapz_lab_block<T>(psi0, I0, I, psi, I0_keep, E, Em64, first, M, nn, dz, partials);
 }
 
 template <typename T>
@@ -1565,10 +1576,12 @@ __global__ __launch_bounds__(256) void k_trapz(
   trapz_block<T>(psi0, I0, I, psi, I0_keep, first, M, nn, dz, partials);
 }
 
-// a9: psi0 <- exp(D_w z_m) * src (element-wise over [N][Nt]); Em = E[m].
+// a9: psi0 <- exp(D_w z_m) * src (element-wise over [N][Nt]); Em = E[m], or Em64
+// (not NULL: the same factor in FP64, product in FP64, for single-precision fields).
 template <typename T>
 __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
-                                                const cplx<T>* __restrict__ Em, long nn, Ctrl* ctrl) {
+                                                const cplx<T>* __restrict__ Em,
+                                                const cplx<double>* __restrict__ Em64, long nn, Ctrl* ctrl) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (ctrl != nullptr && e == 0) {  // fresh control block for the next large step (read back before this launch)
     ctrl->eps = 0.0;
@@ -1578,7 +1591,10 @@ __global__ __launch_bounds__(256) void k_close(const cplx<T>* __restrict__ src, 
     ctrl->pad = 0;
   }
   if (e >= nn) return;
-  dst[e] = Em != nullptr ? cmul(src[e], Em[e]) : src[e];  // no factor: lab-frame iterates are already advanced
+  if (Em64 != nullptr)
+    dst[e] = cround<T>(cmul(cwiden(src[e]), Em64[e]));
+  else
+    dst[e] = Em != nullptr ? cmul(src[e], Em[e]) : src[e];  // no factor: lab-frame iterates are already advanced
 }
 
 // ---------------------------------------------------------------------------
@@ -1629,7 +1645,8 @@ __global__ __launch_bounds__(256) void k_trapz_b(const BatchSlot* __restrict__ s
   const BatchSlot d = slots[blockIdx.y];
   if (d.E != nullptr)  // lab-frame storage
     trapz_lab_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
-                       (cplx<T>*)d.I0_keep, (const cplx<T>*)d.E, d.first, d.m, nn, (T)d.dz, d.partials);
+                       (cplx<T>*)d.I0_keep, (const cplx<T>*)d.E, (const cplx<double>*)d.Em64, d.first, d.m, nn,
+                       (T)d.dz, d.partials);
   else
     trapz_block<T>((const cplx<T>*)d.psi0, (const cplx<T>*)d.I0, (const cplx<T>*)d.I, (cplx<T>*)d.psi,
                    (cplx<T>*)d.I0_keep, d.first, d.m, nn, (T)d.dz, d.partials);

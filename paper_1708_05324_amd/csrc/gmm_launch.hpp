@@ -18,10 +18,10 @@ struct Launch {
                              const cplx<T>* tw, hipStream_t s);
   // E[j][p][k] = exp(i (beta_p(w_k) - beta_0) j dz), j < rows
   static hipError_t phase_table(cplx<T>* E, const double* coef, int nb, int N, int nt, int rows, double dz,
-                                double domega, hipStream_t s);
+                                double domega, hipStream_t s, int j0 = 0);
   // Eigenbasis table of the coupled linear operator: E[j][q][k] = exp(i lam_q(w_k) j dz), j < rows
   static hipError_t phase_table_lam(cplx<T>* E, const double* lam, int N, int nt, int rows, double dz,
-                                    hipStream_t s);
+                                    hipStream_t s, int j0 = 0);
   // back = false: dst = U (E .* src); back = true: dst = conj(E) .* (U^H src), per frequency (E may be null)
   static hipError_t mode_mix(bool back, const cplx<T>* src, long src_jrows, cplx<T>* dst, const cplx<T>* U,
                              const cplx<T>* E, int j0, int N, int nt, int count, const Ctrl* ctrl, hipStream_t s);
@@ -46,12 +46,15 @@ struct Launch {
   static hipError_t spectral_out(int logn, const cplx<T>* in, cplx<T>* out, const cplx<T>* E, int N, int count,
                                  int j0, double domega, double gscale, double inv_omega0, int shock,
                                  const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
-  // E != nullptr: lab-frame iterates (the phase table [M + 1][N][Nt] is applied inside the trapezoid)
+  // E != nullptr: lab-frame iterates (the phase table [M + 1][N][Nt] is applied inside the trapezoid);
+  // Em64 != nullptr (with E): exp(D M dz) in FP64 for the sub-step that ends the large step
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s,
-                          const cplx<T>* E = nullptr);
-  // dst = Em .* src (Em = nullptr: a copy); with ctrl, also resets the control block for the next large step
-  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl, hipStream_t s);
+                          const cplx<T>* E = nullptr, const cplx<double>* Em64 = nullptr);
+  // dst = Em .* src (Em = nullptr: a copy; Em64 != nullptr: the factor and product in FP64); with ctrl, also
+  // resets the control block for the next large step
+  static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl, hipStream_t s,
+                          const cplx<double>* Em64 = nullptr);
   // General-tensor route: pair rows [count][KD][Nt] (x, y and, with Raman, xr, yr), then C = G B and NL.
   static hipError_t pairs_dense(int logn, bool raman, const cplx<T>* A, T* Bd, const int2* pairs, int N, int Np,
                                 int count, int KD, const cplx<T>* Hr, const cplx<T>* tw, const Ctrl* ctrl,

@@ -50,19 +50,19 @@ hipError_t Launch<T>::fft_rows(int logn, int sign, const cplx<T>* in, cplx<T>* o
 
 template <typename T>
 hipError_t Launch<T>::phase_table(cplx<T>* E, const double* coef, int nb, int N, int nt, int rows, double dz,
-                                  double domega, hipStream_t s) {
+                                  double domega, hipStream_t s, int j0) {
   const long total = (long)rows * N * nt;
   hipLaunchKernelGGL((k_phase_table<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, E, coef, nb, N, nt,
-                     total, dz, domega);
+                     total, dz, domega, j0);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::phase_table_lam(cplx<T>* E, const double* lam, int N, int nt, int rows, double dz,
-                                      hipStream_t s) {
+                                      hipStream_t s, int j0) {
   const long total = (long)rows * N * nt;
   hipLaunchKernelGGL((k_phase_table_lam<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, E, lam, N, nt,
-                     total, dz);
+                     total, dz, j0);
   return hipGetLastError();
 }
 
@@ -255,10 +255,10 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
 template <typename T>
 hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi,
                             cplx<T>* I0_keep, int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl,
-                            hipStream_t s, const cplx<T>* E) {
+                            hipStream_t s, const cplx<T>* E, const cplx<double>* Em64) {
   if (E != nullptr)
-    hipLaunchKernelGGL((k_trapz_lab<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, E, first,
-                       M, nn, dz, partials, ctrl);
+    hipLaunchKernelGGL((k_trapz_lab<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, E, Em64,
+                       first, M, nn, dz, partials, ctrl);
   else
     hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, first, M,
                        nn, dz, partials, ctrl);
@@ -267,8 +267,8 @@ hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T
 
 template <typename T>
 hipError_t Launch<T>::close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl,
-                            hipStream_t s) {
-  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, Em, nn, ctrl);
+                            hipStream_t s, const cplx<double>* Em64) {
+  hipLaunchKernelGGL((k_close<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, src, dst, Em, Em64, nn, ctrl);
   return hipGetLastError();
 }
 

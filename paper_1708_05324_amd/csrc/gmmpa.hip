@@ -214,6 +214,8 @@ struct gmm_plan_s {
   void* E = nullptr;    // phase table [E_rows][N][nt]: exp(D_w j dz), built per step size
   int E_rows = 0;
   double E_dz = 0.0;
+  void* E64 = nullptr;  // single-precision fields: [N][nt] row E64_row of the table in FP64
+  int E64_row = -1;
   double* partials = nullptr;
   Ctrl* ctrl = nullptr;
   Ctrl* h_ctrl = nullptr;         // pinned
@@ -238,11 +240,12 @@ int dev_alloc(long long* counter, T** ptr, size_t bytes) {
 }
 
 void free_workspace(gmm_plan_s* P) {
-  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp, &P->Y, &P->E}) {
+  for (void** p : {&P->psi0, &P->I0, &P->psi, &P->work, &P->Bp, &P->Y, &P->E, &P->E64}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
   P->E_rows = 0;
+  P->E64_row = -1;
   if (P->partials) (void)hipFree(P->partials);
   P->partials = nullptr;
   P->cap = 0;
@@ -599,15 +602,41 @@ struct Runner {
     const cplx<T>* I = first ? W + nn : W;
     GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
                                                    (cplx<T>*)P->I0, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl,
-                                                   P->stream, lab_frame(P) ? (const cplx<T>*)P->E : nullptr));
+                                                   P->stream, lab_frame(P) ? (const cplx<T>*)P->E : nullptr,
+                                                   lab_frame(P) ? last_factor(m) : nullptr));
     GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol,
                                                         P->prm.fixed_iters, P->prm.max_iter, P->stream));
     return GMM_OK;
   }
 
-  // Phase factors exp(D_w j dz) for j < rows (FP64 phase, rounded to the field precision).
+  // exp(D_w m dz) in FP64 for the sub-step that ends a large step of m sub-steps (single-precision fields,
+  // full large steps), else nullptr: the table's own row serves.
+  const cplx<double>* last_factor(int m) const {
+    return P->E64 != nullptr && P->E64_row == m ? (const cplx<double>*)P->E64 : nullptr;
+  }
+
+  // Row j of the table in FP64, kept beside it for single-precision fields: the factor that carries the field
+  // from one large step to the next is applied once per step, so its rounding would add up step after step.
+  int ensure_last_factor(int j, double dz) {
+    if (P->E64 == nullptr) {
+      const int rc = dev_alloc(&P->ws_bytes, &P->E64, (size_t)P->N * P->nt * sizeof(cplx<double>));
+      if (rc) return rc;
+    }
+    if (P->cpl_exact)
+      GMM_HIP(Launch<double>::phase_table_lam((cplx<double>*)P->E64, P->lam, P->N, P->nt, 1, dz, P->stream, j));
+    else
+      GMM_HIP(Launch<double>::phase_table((cplx<double>*)P->E64, P->coef, P->nb, P->N, P->nt, 1, dz, P->domega,
+                                          P->stream, j));
+    P->E64_row = j;
+    return GMM_OK;
+  }
+
+  // Phase factors exp(D_w j dz) for j < rows (FP64 phase, rounded to the field precision); for single-precision
+  // fields also row rows - 1 in FP64.
   int ensure_phase_table(int rows, double dz) {
-    if (P->E != nullptr && P->E_rows >= rows && P->E_dz == dz) return GMM_OK;
+    const bool keep64 = sizeof(T) == 4;
+    if (P->E != nullptr && P->E_rows >= rows && P->E_dz == dz)
+      return keep64 && P->E64_row != rows - 1 ? ensure_last_factor(rows - 1, dz) : GMM_OK;
     if (P->E != nullptr && P->E_rows < rows) {
       (void)hipFree(P->E);
       P->ws_bytes -= (long long)P->E_rows * field_bytes(P);
@@ -625,7 +654,7 @@ struct Runner {
       GMM_HIP(Launch<T>::phase_table((cplx<T>*)P->E, P->coef, P->nb, P->N, P->nt, P->E_rows, dz, P->domega,
                                      P->stream));
     P->E_dz = dz;
-    return GMM_OK;
+    return keep64 ? ensure_last_factor(rows - 1, dz) : GMM_OK;
   }
 
   int spec_sums(const cplx<T>* At, double* energy, double* photons) {
@@ -720,7 +749,7 @@ struct Runner {
       // also the next large step's psi(z0) there)
       GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
                                                    lab_frame(P) ? nullptr : (const cplx<T>*)P->E + (size_t)m * nn, nn,
-                                                   P->ctrl, P->stream));
+                                                   P->ctrl, P->stream, lab_frame(P) ? nullptr : last_factor(m)));
       s.large_steps++;
       s.small_steps += m;
       done += m;
@@ -1648,6 +1677,7 @@ struct gmm_batch_s {
   gmm_plan_s* P = nullptr;
   int S = 0, M = 0, nblk = 0;
   void *psi0 = nullptr, *I0 = nullptr, *psi = nullptr, *E = nullptr, *work = nullptr, *Bp = nullptr, *Y = nullptr;
+  void* E64 = nullptr;         // single-precision fields: [S][N][Nt] exp(D_w M dz) per slot in FP64
   double* partials = nullptr;  // [S][nblk][2]
   double* spec = nullptr;      // [S][2][nblk][2]: spectral sums at admission (0) and at the end (1)
   gmm::Ctrl* ctrl = nullptr;   // [S]
@@ -1667,7 +1697,7 @@ namespace {
 
 void batch_free(gmm_batch_s* B) {
   if (!B) return;
-  for (void* p : {B->psi0, B->I0, B->psi, B->E, B->work, B->Bp, B->Y, (void*)B->partials, (void*)B->spec,
+  for (void* p : {B->psi0, B->I0, B->psi, B->E, B->E64, B->work, B->Bp, B->Y, (void*)B->partials, (void*)B->spec,
                   (void*)B->ctrl, (void*)B->rows_d, (void*)B->slots_d})
     if (p) (void)hipFree(p);
   for (void* p : {(void*)B->rows_h, (void*)B->slots_h, (void*)B->ctrl_h, (void*)B->spec_h})
@@ -1681,6 +1711,7 @@ struct BatchRunner {
   gmm_plan_s* P;
   size_t nn() const { return (size_t)P->N * P->nt; }
   cplx<T>* at(void* base, size_t row) const { return (cplx<T>*)base + row * nn(); }
+  cplx<double>* last_factor(int s) const { return (cplx<double>*)B->E64 + (size_t)s * nn(); }
   const cplx<T>* tw() const { return (const cplx<T>*)P->tw; }
 
   int spec_sums_into(int s, int which) {
@@ -1721,6 +1752,9 @@ struct BatchRunner {
     if (!(q.E_dz == dz)) {
       GMM_HIP(Launch<T>::phase_table(at(B->E, (size_t)s * (B->M + 1)), P->coef, P->nb, P->N, P->nt, B->M + 1, dz,
                                      P->domega, P->stream));
+      if (B->E64 != nullptr)
+        GMM_HIP(Launch<double>::phase_table(last_factor(s), P->coef, P->nb, P->N, P->nt, 1, dz, P->domega, P->stream,
+                                            B->M));
       q.E_dz = dz;
     }
     GMM_HIP(gmm::launch_ctrl_reset(B->ctrl + s, P->stream));
@@ -1788,6 +1822,7 @@ struct BatchRunner {
       d.psi = at(B->psi, (size_t)s * M);
       d.I0_keep = at(B->I0, s);
       d.E = at(B->E, (size_t)s * (M + 1));
+      d.Em64 = B->E64 != nullptr && q.m == M ? last_factor(s) : nullptr;
       d.partials = B->partials + (size_t)s * 2 * B->nblk;
       d.ctrl = B->ctrl + s;
       d.dz = q.dz;
@@ -1909,6 +1944,7 @@ int batch_create(gmm_batch* out, gmm_plan_s* P, int slots, int M) {
   };
   if ((rc = dev_alloc(c, &B->psi0, fb * slots)) || (rc = dev_alloc(c, &B->I0, fb * slots)) ||
       (rc = dev_alloc(c, &B->psi, fb * slots * M)) || (rc = dev_alloc(c, &B->E, fb * slots * (M + 1))) ||
+      (P->esz == 4 && (rc = dev_alloc(c, &B->E64, nn * sizeof(gmm::cplx<double>) * slots))) ||
       (rc = dev_alloc(c, &B->work, fb * cap)) || (rc = dev_alloc(c, &B->Bp, bp_bytes(P, cap))) ||
       (P->factored && (rc = dev_alloc(c, &B->Y, (size_t)cap * P->rq * P->nt * P->esz))) ||
       (rc = dev_alloc(c, &B->partials, (size_t)slots * 2 * B->nblk * sizeof(double))) ||

@@ -108,7 +108,8 @@ class Server:
     def _estimate(self, cls) -> int:
         if cls in self.bytes_per_class:
             return self.bytes_per_class[cls]
-        # per slot: psi_0, I_0, M iterates, M + 1 phase rows and M + 1 work rows of N Nt complex values.  Per row
+        # per slot: psi_0, I_0, M iterates, M + 1 phase rows and M + 1 work rows of N Nt complex values (single
+        # precision: and the FP64 factor that ends a large step, two more such rows).  Per row
         # (sub-step of a round): at most 512 Nt bytes of pair rows and 256 Nt of rank-r rows on the routes up to
         # 15 modes, 64 MiB for the plan's constants; on the wide rank-r route (more modes) 4 (Np + 2 RQ) Nt bytes
         # (pair rows / C, Y', Y; RQ = the rank G (2 G - 1) rounded up to 16) and 256 MiB for the constants and
@@ -117,7 +118,7 @@ class Server:
         N = synth.n_modes_for_groups(groups)
         c = 16 if self.precision == "fp64" else 8
         rows = self.slots * (self.M + 1)
-        fields = self.slots * (3 * self.M + 4) * N * nt * c
+        fields = self.slots * (3 * self.M + 4 + (0 if c == 16 else 2)) * N * nt * c
         if N <= 15:
             return int(fields + rows * (512 + 256) * nt + (64 << 20))
         Np, rq = N * (N + 1) // 2, -(-groups * (2 * groups - 1) // 16) * 16
