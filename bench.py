@@ -31,11 +31,13 @@ PEAKS = {  # MI355X published dense peaks
     "mfma_bf16_TFLOPs": 2500.0,
     # three bf16 products per useful multiply-add: useful-work peak of the split contraction
     "mfma_bf16x3_TFLOPs": 2500.0 / 3.0,
+    # four on the rank-r route's contraction and projection (a third plane of the fixed factor)
+    "mfma_bf16x4_TFLOPs": 2500.0 / 4.0,
     # vector ALU with packed FP32 disabled: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
     "alu_fp32_TFLOPs": 78.6,
     "alu_fp64_TFLOPs": 78.6,
 }
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-5}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32"}
 
 
@@ -45,8 +47,9 @@ def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0, route: s
 
     rank > 0: the plan contracts through the factor S^ = U V (U: Np x r), so the
     Raman convolution acts on r rows and the products are 2 r Np Nt each.
-    bf16x3 executes three bf16 products per useful multiply-add; the useful
-    count is what is reported (against the matching useful-work peak).  The
+    bf16x3 executes three bf16 products per useful multiply-add (four in the
+    rank-r contraction and projection, whose fixed factor has a third plane);
+    the useful count is what is reported (against the matching useful-work peak).  The
     sub-step transforms and the spectral output also read the phase table
     (one complex per element)."""
     Np = N * (N + 1) // 2
@@ -273,8 +276,8 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
     wk = work_per_eval(kind, N, Nt, prec, rank, route)
     sec = total_ms * 1e-3
     if wk["compute"] == "mfma":
-        cpeak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else
-                      "mfma_bf16x3_TFLOPs" if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
+        split = "mfma_bf16x4_TFLOPs" if rank and kind in ("contract", "project") else "mfma_bf16x3_TFLOPs"
+        cpeak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else split if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
     else:
         cpeak = PEAKS["alu_fp64_TFLOPs" if prec == "fp64" else "alu_fp32_TFLOPs"]
     t_compute = wk["flops"] / (cpeak * 1e12)
@@ -448,8 +451,9 @@ def bench_configs() -> dict:
 
 def bench_full_length() -> dict:
     """The metric workload over its full 1 m (about 110 000 small steps) in FP64
-    (tol 1e-12), FP32 (1e-6) and BF16X3 (3e-5): each precision's field error at
-    1 m against the FP64 run (whose first 2 mm match the oracle to 1.3e-14), and
+    (tol 1e-12), and FP32 and BF16X3 over a range of stopping tolerances (the
+    defaults first): each run's field error at 1 m against the FP64 run (whose
+    first 2 mm match the oracle to 1.3e-14), and
     the conditioning at 1 m: the FP64 run again from the launch field perturbed
     by 1e-12 relative (seeded), kappa = (change at 1 m) / 1e-12."""
     import numpy as np
@@ -457,8 +461,8 @@ def bench_full_length() -> dict:
     from paper_1708_05324_amd import gmmpa, synth
     w = synth.config3()
 
-    def run(prec, A0):
-        plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30)
+    def run(prec, A0, tol=None):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec] if tol is None else tol, max_iter=30)
         dtype = torch.complex128 if prec == "fp64" else torch.complex64
         A = torch.from_numpy(A0).to(device="cuda", dtype=dtype)
         torch.cuda.synchronize()
@@ -479,10 +483,14 @@ def bench_full_length() -> dict:
            "config": {"workload": "grin15_raman_nt16384", "L_m": w.L, "dz_um": round(w.dz * 1e6, 4), "M": w.M},
            "fp64": r64}
     peak = float(np.max(np.abs(ref)))
-    for prec in ("fp32", "bf16x3"):
-        f, r = run(prec, w.A0)
-        r["field_error_vs_fp64"] = float(np.max(np.abs(f - ref)) / peak)
-        out[prec] = r
+    for prec, tols in (("fp32", (1e-6, 1e-7, 3e-8)), ("bf16x3", (3e-5, 1e-5, 3e-6, 1e-6, 1e-7))):
+        out[prec] = []
+        for tol in tols:
+            f, r = run(prec, w.A0, tol)
+            r["tol"] = tol
+            r["field_error_vs_fp64"] = float(np.max(np.abs(f - ref)) / peak)
+            out[prec].append(r)
+            print(json.dumps({prec: r}), file=sys.stderr, flush=True)
     eta = np.random.default_rng(synth.SEED_BASE + 7000).standard_normal(w.A0.shape)
     fp, _ = run("fp64", w.A0 * (1.0 + 1e-12 * eta))
     out["kappa_1m_fp64"] = float(np.max(np.abs(fp - ref)) / peak / 1e-12)

@@ -717,9 +717,12 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
 // its own LDS slab (transposed, so that each lane reads its column as 16-byte
 // vectors) and folds them into NL.  After the factor U has been staged in LDS
 // the waves never wait for each other.
-//   BF16: U and Y' as hi/lo planes; v_mfma_f32_16x16x32_bf16, products
-//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  Y' planes of words
-//         [count][32][Nt] (word i holds rows 2i and 2i + 1), kv valid rows.
+//   BF16: Y' as hi/lo planes, U (fixed) as hi/lo/lo2 planes; v_mfma_f32_16x16x32_bf16,
+//         products U^hi Y^hi + U^hi Y^lo + U^lo Y^hi + U^lo2 Y^hi, FP32 accumulation.
+//         U's third plane removes the residual of its two-plane split (up to
+//         2^-18 of each entry), which would recur in every evaluation as a fixed
+//         change of the coupling.  Y' planes of words [count][32][Nt] (word i
+//         holds rows 2i and 2i + 1), kv valid rows.
 //   FP32: v_mfma_f32_16x16x4f32.  Y' [count][kv][Nt], rows clamped to kv - 1
 //         (U is zero there).
 __host__ __device__ constexpr int tri_mode_l(int Q) {
@@ -754,8 +757,8 @@ struct ColShape {
   static constexpr int LMAX = tri_mode_l(RPAD);        // most modes whose pairs fit in RPAD rows
   static constexpr int NP_MAX = LMAX * (LMAX + 1) / 2;  // rows beyond are padding (zero rows of U)
   static constexpr int SLAB = 20;                       // floats per column of a wave's C slab (16 + pad)
-  // U: BF16 [2][RPAD][9] 16-byte chunks (one pad chunk per row); FP32 [K][RPAD + 16]
-  static constexpr size_t u_bytes() { return BF16 ? (size_t)2 * RPAD * 9 * 16 : (size_t)K * (RPAD + 16) * 4; }
+  // U: BF16 [3][RPAD][9] 16-byte chunks (hi, lo, lo2; one pad chunk per row); FP32 [K][RPAD + 16]
+  static constexpr size_t u_bytes() { return BF16 ? (size_t)3 * RPAD * 9 * 16 : (size_t)K * (RPAD + 16) * 4; }
   static constexpr size_t lds_bytes() { return u_bytes() + (size_t)4 * 64 * SLAB * 4; }
 };
 
@@ -779,10 +782,10 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
   if constexpr (BF16) {
     uint4* sU = reinterpret_cast<uint4*>(smem_raw);
     const uint4* uh = reinterpret_cast<const uint4*>(Ua);
-    const uint4* ul = reinterpret_cast<const uint4*>(Ub);
-    for (int i = tid; i < 2 * RPAD * 8; i += 256) {
+    const uint4* ul = reinterpret_cast<const uint4*>(Ub);  // lo, then lo2
+    for (int i = tid; i < 3 * RPAD * 8; i += 256) {
       const int plane = i / (RPAD * 8), r = (i / 8) % RPAD, c = i % 8;
-      sU[(plane * RPAD + r) * 9 + c] = (plane ? ul : uh)[r * 8 + c];
+      sU[(plane * RPAD + r) * 9 + c] = plane ? ul[((plane - 1) * RPAD + r) * 8 + c] : uh[r * 8 + c];
     }
   } else {
     float* sU = reinterpret_cast<float*>(smem_raw);
@@ -852,11 +855,13 @@ __global__ __launch_bounds__(256, 2) void k_contract_cols(
             const int r = 16 * G + lr;
             const bf16x8 uh = __builtin_bit_cast(bf16x8, sU[r * 9 + 4 * ks + lk]);
             const bf16x8 ul = __builtin_bit_cast(bf16x8, sU[(RPAD + r) * 9 + 4 * ks + lk]);
+            const bf16x8 ul2 = __builtin_bit_cast(bf16x8, sU[(2 * RPAD + r) * 9 + 4 * ks + lk]);
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yh[cb][ks], acc[cb], 0, 0, 0);
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh, yl[cb][ks], acc[cb], 0, 0, 0);
               acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul, yh[cb][ks], acc[cb], 0, 0, 0);
+              acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul2, yh[cb][ks], acc[cb], 0, 0, 0);
             }
           }
         } else {
@@ -968,8 +973,9 @@ __global__ __launch_bounds__(256) void k_project(
 // (triangular pair order; pairs beyond Np are zero).  A chunk goes through the
 // wave's own LDS slab, transposed into MFMA operand layout, and is multiplied
 // by V (staged in LDS once per block).  Y [count][RQ][Nt] in FP32.
-//   BF16: B and V split as hi + lo, v_mfma_f32_16x16x32_bf16, products
-//         hi*hi + hi*lo + lo*hi, FP32 accumulation.  V hi/lo [RQ][KPAD] bf16.
+//   BF16: B split as hi + lo, V (fixed) as hi + lo + lo2, v_mfma_f32_16x16x32_bf16,
+//         products V^hi B^hi + V^hi B^lo + V^lo B^hi + V^lo2 B^hi, FP32
+//         accumulation.  V hi [RQ][KPAD] bf16, lo and lo2 [2][RQ][KPAD].
 //   FP32: v_mfma_f32_16x16x4f32.  V^T [KPAD][RQ].
 template <int RQ, int KPAD, bool BF16>
 struct ProjShape {
@@ -980,7 +986,7 @@ struct ProjShape {
   static constexpr int NP_MAX = LMAX * (LMAX + 1) / 2;
   static constexpr int VS = BF16 ? KPAD / 8 + 1 : (RQ <= 16 ? 16 : 80);  // V row stride (16-byte chunks | floats)
   static constexpr int SS = BF16 ? 5 : 36;  // slab stride per column (16-byte chunks per plane | floats)
-  static constexpr size_t v_bytes() { return BF16 ? (size_t)2 * RQ * VS * 16 : (size_t)KPAD * VS * 4; }
+  static constexpr size_t v_bytes() { return BF16 ? (size_t)3 * RQ * VS * 16 : (size_t)KPAD * VS * 4; }
   static constexpr size_t slab_bytes() { return BF16 ? (size_t)2 * 64 * SS * 16 : (size_t)64 * SS * 4; }
   static constexpr size_t lds_bytes() { return v_bytes() + 4 * slab_bytes(); }
 };
@@ -1000,11 +1006,11 @@ __global__ __launch_bounds__(256, 2) void k_project_cols(
   if constexpr (BF16) {
     uint4* sV = reinterpret_cast<uint4*>(smem_raw);
     const uint4* vh = reinterpret_cast<const uint4*>(Va);
-    const uint4* vl = reinterpret_cast<const uint4*>(Vb);
+    const uint4* vl = reinterpret_cast<const uint4*>(Vb);  // lo, then lo2
     constexpr int KC = KPAD / 8;
-    for (int i = tid; i < 2 * RQ * KC; i += 256) {
+    for (int i = tid; i < 3 * RQ * KC; i += 256) {
       const int plane = i / (RQ * KC), r = (i / KC) % RQ, c = i % KC;
-      sV[(plane * RQ + r) * VS + c] = (plane ? vl : vh)[r * KC + c];
+      sV[(plane * RQ + r) * VS + c] = plane ? vl[((plane - 1) * RQ + r) * KC + c] : vh[r * KC + c];
     }
   } else {
     float* sV = reinterpret_cast<float*>(smem_raw);
@@ -1052,11 +1058,12 @@ __global__ __launch_bounds__(256, 2) void k_project_cols(
           }
           __builtin_amdgcn_wave_barrier();
           const uint4* sV = reinterpret_cast<const uint4*>(smem_raw);
-          bf16x8 vh[RB], vl[RB];
+          bf16x8 vh[RB], vl[RB], vl2[RB];
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
             vh[rb] = __builtin_bit_cast(bf16x8, sV[(rb * 16 + lr) * VS + 4 * C + lk]);
             vl[rb] = __builtin_bit_cast(bf16x8, sV[(RQ + rb * 16 + lr) * VS + 4 * C + lk]);
+            vl2[rb] = __builtin_bit_cast(bf16x8, sV[(2 * RQ + rb * 16 + lr) * VS + 4 * C + lk]);
           }
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb) {
@@ -1067,6 +1074,7 @@ __global__ __launch_bounds__(256, 2) void k_project_cols(
               acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[rb], bh, acc[rb][cb], 0, 0, 0);
               acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[rb], bl, acc[rb][cb], 0, 0, 0);
               acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl[rb], bh, acc[rb][cb], 0, 0, 0);
+              acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl2[rb], bh, acc[rb][cb], 0, 0, 0);
             }
           }
         } else {
@@ -1525,20 +1533,42 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
     if (first) I0_keep[e] = i0;
     const cplx<T> h0 = cscale(i0, T(0.5));
     cplx<T> run = {0, 0};
-    for (int j = 0; j < M; ++j) {
-      const bool wide = Em64 != nullptr && j == M - 1;
-      const cplx<double> e64 = wide ? Em64[e] : cplx<double>{0.0, 0.0};
-      const cplx<T> ej = wide ? cplx<T>{(T)e64.re, (T)e64.im} : E[(size_t)(j + 1) * nn + e];
-      const cplx<T> ij = cmul(I[(size_t)j * nn + e], cplx<T>{ej.re, -ej.im});
-      cplx<T> acc = cadd(cadd(h0, run), cscale(ij, T(0.5)));
-      const cplx<T> x = {p0.re + dz * acc.re, p0.im + dz * acc.im};
-      const cplx<T> nw = wide ? cround<T>(cmul(cwiden(x), e64)) : cmul(x, ej);
-      run = cadd(run, ij);
-      const cplx<T> old = !first ? psi[(size_t)j * nn + e] : wide ? cround<T>(cmul(cwiden(p0), e64)) : cmul(p0, ej);
-      const double dr = (double)nw.re - (double)old.re, di = (double)nw.im - (double)old.im;
-      d += dr * dr + di * di;
-      s += (double)nw.re * nw.re + (double)nw.im * nw.im;
-      psi[(size_t)j * nn + e] = nw;
+    const cplx<double> e64 = Em64 != nullptr ? Em64[e] : cplx<double>{0.0, 1.0};
+    // Sub-steps in chunks of four: a chunk's loads are all issued before its arithmetic, so four
+    // round trips to memory overlap instead of one per sub-step.
+    constexpr int U = 4;
+    for (int j0 = 0; j0 < M; j0 += U) {
+      cplx<T> ej[U], in[U], po[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u;
+        if (j < M) {
+          ej[u] = Em64 != nullptr && j == M - 1 ? cplx<T>{(T)e64.re, (T)e64.im} : E[(size_t)(j + 1) * nn + e];
+          in[u] = I[(size_t)j * nn + e];
+          if (!first) po[u] = psi[(size_t)j * nn + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u;
+        if (j >= M) break;
+        const cplx<T> ij = cmul(in[u], cplx<T>{ej[u].re, -ej[u].im});
+        const cplx<T> acc = cadd(cadd(h0, run), cscale(ij, T(0.5)));
+        run = cadd(run, ij);
+        const cplx<T> x = {p0.re + dz * acc.re, p0.im + dz * acc.im};
+        cplx<T> nw, old;
+        if (Em64 != nullptr && j == M - 1) {  // the step's last factor and products in FP64
+          nw = cround<T>(cmul(cwiden(x), e64));
+          old = first ? cround<T>(cmul(cwiden(p0), e64)) : po[u];
+        } else {
+          nw = cmul(x, ej[u]);
+          old = first ? cmul(p0, ej[u]) : po[u];
+        }
+        const double dr = (double)nw.re - (double)old.re, di = (double)nw.im - (double)old.im;
+        d += dr * dr + di * di;
+        s += (double)nw.re * nw.re + (double)nw.im * nw.im;
+        psi[(size_t)j * nn + e] = nw;
+      }
     }
   }
   red[0][threadIdx.x] = d;

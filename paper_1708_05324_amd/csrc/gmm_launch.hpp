@@ -95,14 +95,15 @@ hipError_t launch_contract_bf16(int rt, int kpad, const void* Shi, const void* S
                                 const uint32_t* Blo, cplx<float>* A_NL, const int* pidx, int N, int Nt, int count,
                                 const Ctrl* ctrl, hipStream_t s);
 // Column-owner contraction of the rank-r route (complex64 fields, Rpad 64 or 128,
-// K = 64): BF16 split (Ua/Ub = U hi/lo [Rpad][64] bf16, Ya/Yb = Y' planes of
+// K = 64): BF16 split (Ua = U hi [Rpad][64] bf16, Ub = its lo and lo2 planes [2][Rpad][64], Ya/Yb = Y' planes of
 // 2-row words, kv valid rows) or FP32 (Ua = U^T [64][Rpad], Ya = Y' [count][kv][Nt]).
 // col_blocks: tiles of 16 col_blocks columns (4: 64, 3: 48).
 hipError_t launch_contract_cols(int rpad, bool bf16, const void* Ua, const void* Ub, const void* Ya, const void* Yb,
                                 cplx<float>* A_NL, int N, int kv, int Nt, int count, const Ctrl* ctrl,
                                 hipStream_t s, int blocks_per_cu = 0, int col_blocks = 4);
 // Column-owner projection Y = V B of the rank-r route (complex64 fields, RQ <= 64,
-// KPAD 64 or 128): BF16 split (Va/Vb = V hi/lo [RQ][KPAD] bf16) or FP32 (Va = V^T [KPAD][RQ]).
+// KPAD 64 or 128): BF16 split (Va = V hi [RQ][KPAD] bf16, Vb = its lo and lo2 planes [2][RQ][KPAD]) or FP32
+// (Va = V^T [KPAD][RQ]).
 hipError_t launch_project_cols(int rq, int kpad, bool bf16, const void* Va, const void* Vb, const cplx<float>* A,
                                float* Y, int N, int Nt, int count, const Ctrl* ctrl, hipStream_t s);
 // General-route product C = G B with the BF16 split for BF16X3 plans (up to 15 modes; G hi/lo

@@ -167,9 +167,9 @@ struct gmm_plan_s {
   void* VT = nullptr;      // [kp][rq] V transposed, field precision
   void* UT = nullptr;      // [64][rpad] U transposed (contraction operand, K = 64)
   void* Uhi = nullptr;     // [rpad][64] bf16 split of U, K contiguous (BF16X3)
-  void* Ulo = nullptr;
+  void* Ulo = nullptr;     // [2][rpad][64]: the lo and lo2 planes
   void* Vhi = nullptr;     // [rq][kp] bf16 split of V, pair index contiguous (BF16X3)
-  void* Vlo = nullptr;
+  void* Vlo = nullptr;     // [2][rq][kp]: the lo and lo2 planes
   void* Y = nullptr;       // workspace [cap][rq][nt]: Y = V B
   // wide rank-r route (complex64 fields, N up to 55): both products on rocBLAS, see gmm_wide.hip
   bool wide = false;
@@ -1170,26 +1170,32 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
   GMM_HIP(hipMemcpy(P->VT, vt.data(), vt.size() * sizeof(T), hipMemcpyHostToDevice));
   GMM_HIP(hipMemcpy(P->UT, ut.data(), ut.size() * sizeof(T), hipMemcpyHostToDevice));
   if (P->bf16) {
-    std::vector<uint16_t> hi((size_t)P->rpad * 64, 0), lo((size_t)P->rpad * 64, 0);
+    // fixed factors in three bf16 planes: x = hi + lo + lo2 to about 2^-26 of x (two planes leave up to 2^-18,
+    // the same in every evaluation)
+    auto split3 = [](double v, uint16_t* h, uint16_t* l, uint16_t* l2) {
+      *h = host_bf16((float)v);
+      const double r1 = v - (double)host_bf16_value(*h);
+      *l = host_bf16((float)r1);
+      *l2 = host_bf16((float)(r1 - (double)host_bf16_value(*l)));
+    };
+    const size_t un = (size_t)P->rpad * 64;
+    std::vector<uint16_t> hi(un, 0), lo(2 * un, 0);
     for (int row = 0; row < Np; ++row)
       for (int rho = 0; rho < r; ++rho) {
-        const float x = (float)U[(size_t)row * r + rho];
-        const uint16_t h = host_bf16(x);
-        hi[(size_t)row * 64 + rho] = h;
-        lo[(size_t)row * 64 + rho] = host_bf16(x - host_bf16_value(h));
+        const size_t o = (size_t)row * 64 + rho;
+        split3(U[(size_t)row * r + rho], &hi[o], &lo[o], &lo[un + o]);
       }
     if ((rc = dev_alloc(&P->const_bytes, &P->Uhi, hi.size() * 2)) ||
         (rc = dev_alloc(&P->const_bytes, &P->Ulo, lo.size() * 2)))
       return rc;
     GMM_HIP(hipMemcpy(P->Uhi, hi.data(), hi.size() * 2, hipMemcpyHostToDevice));
     GMM_HIP(hipMemcpy(P->Ulo, lo.data(), lo.size() * 2, hipMemcpyHostToDevice));
-    std::vector<uint16_t> vh((size_t)rq * kp, 0), vl((size_t)rq * kp, 0);
+    const size_t vn = (size_t)rq * kp;
+    std::vector<uint16_t> vh(vn, 0), vl(2 * vn, 0);
     for (int rho = 0; rho < r; ++rho)
       for (int Q = 0; Q < Np; ++Q) {
-        const float x = (float)V[(size_t)rho * Np + Q];
-        const uint16_t h = host_bf16(x);
-        vh[(size_t)rho * kp + Q] = h;
-        vl[(size_t)rho * kp + Q] = host_bf16(x - host_bf16_value(h));
+        const size_t o = (size_t)rho * kp + Q;
+        split3(V[(size_t)rho * Np + Q], &vh[o], &vl[o], &vl[vn + o]);
       }
     if ((rc = dev_alloc(&P->const_bytes, &P->Vhi, vh.size() * 2)) ||
         (rc = dev_alloc(&P->const_bytes, &P->Vlo, vl.size() * 2)))

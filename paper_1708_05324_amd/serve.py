@@ -27,7 +27,7 @@ import numpy as np
 
 from . import gmmpa, synth
 
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-5}
 
 
 def step_for(req, template) -> float:

@@ -58,7 +58,7 @@ def test_batch_equals_solo_bitwise(torch_gpu, prec, fixed, tuned):
     from paper_1708_05324_amd import gmmpa
     torch = torch_gpu
     w = synth.config2()                                 # 6 modes, 2^13 samples, packed route, Raman + shock
-    tol = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}[prec]
+    tol = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-5}[prec]
     plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30, fixed_iters=fixed)
     if tuned:                                           # the tuned launch is the plan's: batch and solo share it
         choice, us = plan.autotune(3 * (w.M + 1))
@@ -94,7 +94,7 @@ def test_batch_equals_solo_bitwise_rank_route(torch_gpu, prec):
     torch = torch_gpu
     w = synth.grin_workload(3, 5, 2 ** 13, synth.DT_FINE, "gaussian", 200e-15, energy=100e-9, fR=0.18,
                             self_steepening=1, M=10, L=1.0)
-    tol = {"fp32": 1e-6, "bf16x3": 3e-5}[prec]
+    tol = {"fp32": 1e-6, "bf16x3": 1e-5}[prec]
     plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
     assert plan.rank() == 45
     ref = O.mpa_propagate(w.A0, O.model_from_workload(w), w.M * w.dz, w.dz, w.M, fixed_iters=3)

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "metric_22_large_steps.npz")
-TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5}          # iteration thresholds the benchmark uses
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-5}          # iteration thresholds the benchmark uses
 BOUND = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}        # stated field tolerances vs the FP64 oracle
 # measured level of the current kernels (about 3x headroom): a regression far below the stated bounds shows here
 REGRESSION = {"fp64": 1e-12, "fp32": 2.5e-6, "bf16x3": 5e-6}

@@ -98,7 +98,7 @@ def test_wide_route_tolerance_mode_and_batch_equal_alone(torch_gpu):
     from paper_1708_05324_amd import gmmpa
     torch = torch_gpu
     w = workload(7, 512, dt=20e-15)
-    plan = gmmpa.plan_from_workload(w, precision="bf16x3", tol=3e-5, max_iter=30)
+    plan = gmmpa.plan_from_workload(w, precision="bf16x3", tol=1e-5, max_iter=30)
     assert plan.rank() == 91
     A0 = to_dev(torch, w.A0)
     lengths = [6 * w.dz, 9 * w.dz]
@@ -156,7 +156,7 @@ def test_wide_route_at_the_largest_served_shape(torch_gpu):
     w = synth.wide_workload(2 ** 15)
     L = 2 * w.M * w.dz
     out = {}
-    for prec, tol in (("bf16x3", 3e-5), ("fp32", 1e-6)):
+    for prec, tol in (("bf16x3", 1e-5), ("fp32", 1e-6)):
         plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
         assert plan.rank() == 190
         res = plan.propagate(to_dev(torch, w.A0), L, w.dz, w.M)
