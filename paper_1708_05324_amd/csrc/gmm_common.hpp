@@ -38,6 +38,7 @@ struct BatchSlot {
                       // (the sub-step that ends the step multiplies in FP64), else NULL
   double* partials;   // [trapz_blocks(N Nt)][2] FP64 partial sums of the norm
   Ctrl* ctrl;         // the slot's control block
+  Ctrl* ctrl_host;    // its mirror in pinned host memory (device-visible address), stored by the norm
   double dz;
   int first, m;
 };

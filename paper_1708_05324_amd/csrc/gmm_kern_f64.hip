@@ -8,9 +8,12 @@ namespace gmm {
 // Fixed-order reduction of the partial sums and the stopping decision: thread
 // t adds partials t, t + 256, ... in order, each wave reduces its 64 sums by a
 // butterfly of lane shuffles (the same pairing every launch: deterministic),
-// and thread 0 adds the four wave sums in wave order after one barrier.
+// and thread 0 adds the four wave sums in wave order after one barrier.  With
+// `host` (pinned host memory mapped for the device), thread 0 also stores the
+// updated control block there, so the host reads it once the launch is done
+// instead of queueing a copy after every iteration.
 __device__ __forceinline__ void norm_final_block(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
-                                                 double tol, int fixed_iters, int max_iter) {
+                                                 Ctrl* host, double tol, int fixed_iters, int max_iter) {
   __shared__ double wsum[2][4];
   double d = 0.0, s = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += 256) {
@@ -46,20 +49,21 @@ __device__ __forceinline__ void norm_final_block(const double* __restrict__ part
       ctrl->status = 1;
       ctrl->done = 1;
     }
+    if (host != nullptr) *host = *ctrl;
   }
 }
 
 __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partials, int nblocks, Ctrl* ctrl,
-                                                     double tol, int fixed_iters, int max_iter) {
+                                                     Ctrl* host, double tol, int fixed_iters, int max_iter) {
   if (skip_iteration(ctrl)) return;
-  norm_final_block(partials, nblocks, ctrl, tol, fixed_iters, max_iter);
+  norm_final_block(partials, nblocks, ctrl, host, tol, fixed_iters, max_iter);
 }
 
 // One block per slot of a batched round.
 __global__ __launch_bounds__(256) void k_norm_final_b(const BatchSlot* __restrict__ slots, int nblocks, double tol,
                                                        int fixed_iters, int max_iter) {
   const BatchSlot d = slots[blockIdx.x];
-  norm_final_block(d.partials, nblocks, d.ctrl, tol, fixed_iters, max_iter);
+  norm_final_block(d.partials, nblocks, d.ctrl, d.ctrl_host, tol, fixed_iters, max_iter);
 }
 
 __global__ void k_ctrl_reset(Ctrl* ctrl) {
@@ -74,8 +78,9 @@ __global__ void k_ctrl_reset(Ctrl* ctrl) {
 
 
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
-                             int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, partials, nblocks, ctrl, tol, fixed_iters, max_iter);
+                             int max_iter, hipStream_t s, Ctrl* host) {
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, partials, nblocks, ctrl, host, tol, fixed_iters,
+                     max_iter);
   return hipGetLastError();
 }
 // k_gain_matrix: the per-sub-step matrix of the linear-in-A terms of Sec. III.F,

@@ -1455,6 +1455,27 @@ __global__ __launch_bounds__((FftShape<LOGN, (int)sizeof(T), kSpectralLogR<LOGN>
   spectral_out_row<T, LOGN>(in + row, out + row, ph, domega, gscale, inv_omega0, shock, lds, threadIdx.x, tw);
 }
 
+// Sums (d, s) over the 256 threads of a block in a fixed order and stores them
+// as the block's partial pair: a butterfly of lane shuffles within each wave,
+// then thread 0 adds the four wave sums in wave order after one barrier.
+__device__ __forceinline__ void block_sum2_store(double d, double s, double* __restrict__ partials) {
+  __shared__ double wsum[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o);
+    s += __shfl_xor(s, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[0][threadIdx.x >> 6] = d;
+    wsum[1][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+    partials[2 * blockIdx.x + 1] = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a7 + a8: cumulative trapezoid and the relative change of psi (FP64 sums).
 //   psi_j^(n+1) = psi_0 + dz [ I_0/2 + sum_{k<j} I_k + I_j/2 ],  j = 1..M
@@ -1466,7 +1487,6 @@ __device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, co
                                             const cplx<T>* __restrict__ I, cplx<T>* __restrict__ psi,
                                             cplx<T>* __restrict__ I0_keep, int first, int M, long nn, T dz,
                                             double* __restrict__ partials) {
-  __shared__ double red[2][256];
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
   if (e < nn) {
@@ -1487,20 +1507,7 @@ __device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, co
       psi[(size_t)j * nn + e] = nw;
     }
   }
-  red[0][threadIdx.x] = d;
-  red[1][threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = red[0][0];
-    partials[2 * blockIdx.x + 1] = red[1][0];
-  }
+  block_sum2_store(d, s, partials);
 }
 
 // Lab-frame storage (used when the gain and coupling terms are off): the
@@ -1524,7 +1531,6 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
                                                 cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
                                                 const cplx<double>* __restrict__ Em64, int first, int M, long nn,
                                                 T dz, double* __restrict__ partials) {
-  __shared__ double red[2][256];
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
   if (e < nn) {
@@ -1571,20 +1577,7 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
       }
     }
   }
-  red[0][threadIdx.x] = d;
-  red[1][threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = red[0][0];
-    partials[2 * blockIdx.x + 1] = red[1][0];
-  }
+  block_sum2_store(d, s, partials);
 }
 
 template <typename T>

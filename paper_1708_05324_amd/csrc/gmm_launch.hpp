@@ -129,7 +129,8 @@ hipError_t launch_conv_bf16(int logn, const float* Y, uint32_t* Bhi, uint32_t* B
                             const cplx<float>* Gs, const cplx<float>* tw, const Ctrl* ctrl, hipStream_t s);
 
 hipError_t launch_norm_final(const double* partials, int nblocks, Ctrl* ctrl, double tol, int fixed_iters,
-                             int max_iter, hipStream_t s);
+                             int max_iter, hipStream_t s,
+                             Ctrl* host = nullptr);
 hipError_t launch_ctrl_reset(Ctrl* ctrl, hipStream_t s);
 
 // Wide rank-r route (complex64 fields, N <= wide_max_modes(); gmm_wide.hip).

@@ -218,7 +218,8 @@ struct gmm_plan_s {
   int E64_row = -1;
   double* partials = nullptr;
   Ctrl* ctrl = nullptr;
-  Ctrl* h_ctrl = nullptr;         // pinned
+  Ctrl* h_ctrl = nullptr;         // pinned, mapped: the norm kernel stores the control block here
+  Ctrl* h_ctrl_dev = nullptr;     // its device-visible address
   hipEvent_t ev = nullptr;        // marks the stop-flag copy the host waits for
   double* h_partials = nullptr;   // pinned
   long long const_bytes = 0, ws_bytes = 0;
@@ -605,7 +606,8 @@ struct Runner {
                                                    P->stream, lab_frame(P) ? (const cplx<T>*)P->E : nullptr,
                                                    lab_frame(P) ? last_factor(m) : nullptr));
     GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol,
-                                                        P->prm.fixed_iters, P->prm.max_iter, P->stream));
+                                                        P->prm.fixed_iters, P->prm.max_iter, P->stream,
+                                                        P->h_ctrl_dev));
     return GMM_OK;
   }
 
@@ -707,20 +709,19 @@ struct Runner {
           P->prof.cur_iter = n_enq + 1;
           if ((rc = iteration(m, dz, n_enq == 0))) return rc;
         }
-        GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
-        GMM_HIP(hipStreamSynchronize(P->stream));
+        GMM_HIP(hipStreamSynchronize(P->stream));  // the last norm stored the control block in h_ctrl
       } else {
         // Queue the first iteration and the first half of the second; then, per
-        // iteration n: wait for the flag read after iteration n's norm while the
-        // GPU runs the first half of iteration n + 1, and queue its second half
-        // and the first half of iteration n + 2 only if not converged.  After
-        // convergence only one half-iteration is queued for nothing, and its
-        // launches exit at once (device-side guard).
+        // iteration n: wait for iteration n's norm (which stores the control
+        // block in pinned host memory) while the GPU runs the first half of
+        // iteration n + 1, and queue its second half and the first half of
+        // iteration n + 2 only if not converged.  After convergence only one
+        // half-iteration is queued for nothing, and its launches exit at once
+        // (device-side guard).
         P->prof.cur_iter = 1;
         if ((rc = iteration(m, dz, true))) return rc;
         n_enq = 1;
         for (;;) {
-          GMM_HIP(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
           GMM_HIP(hipEventRecord(P->ev, P->stream));
           const bool more = n_enq < P->prm.max_iter;
           if (more) {
@@ -1644,10 +1645,12 @@ int create(gmm_plan* out, const gmm_params* p, const double* betas, const double
   if (hipEventCreateWithFlags(&P->ev, hipEventDisableTiming) != hipSuccess)
     return bail(fail(GMM_ERR_HIP, "hipEventCreate failed"));
   if ((rc = dev_alloc(&P->const_bytes, &P->ctrl, sizeof(Ctrl)))) return bail(rc);
-  if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void**)&P->h_partials, 2 * sizeof(double) * gmm::trapz_blocks((long)N * nt),
                     hipHostMallocDefault) != hipSuccess)
     return bail(fail(GMM_ERR_NOMEM, "pinned host allocation failed"));
+  if (hipHostGetDevicePointer((void**)&P->h_ctrl_dev, P->h_ctrl, 0) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "hipHostGetDevicePointer of the control block failed"));
   *out = P;
   g_last_error.clear();
   return GMM_OK;
@@ -1691,7 +1694,8 @@ struct gmm_batch_s {
   gmm::BatchSlot* slots_d = nullptr;  // [2 S]: iterating slots, then closing slots
   gmm::BatchRow* rows_h = nullptr;    // pinned mirrors
   gmm::BatchSlot* slots_h = nullptr;
-  gmm::Ctrl* ctrl_h = nullptr;
+  gmm::Ctrl* ctrl_h = nullptr;        // mapped: the norm kernel stores each slot's control block here
+  gmm::Ctrl* ctrl_h_dev = nullptr;    // its device-visible address
   double* spec_h = nullptr;
   std::vector<BatchSlotState> slot;
   std::vector<int> round;       // slots iterating in the queued round
@@ -1831,6 +1835,7 @@ struct BatchRunner {
       d.Em64 = B->E64 != nullptr && q.m == M ? last_factor(s) : nullptr;
       d.partials = B->partials + (size_t)s * 2 * B->nblk;
       d.ctrl = B->ctrl + s;
+      d.ctrl_host = B->ctrl_h_dev + s;
       d.dz = q.dz;
       d.first = q.first ? 1 : 0;
       d.m = q.m;
@@ -1871,7 +1876,6 @@ struct BatchRunner {
       GMM_HIP(gmm::launch_norm_final_b(B->slots_d, ns, B->nblk, P->prm.tol, P->prm.fixed_iters, P->prm.max_iter,
                                        P->stream));
     }
-    GMM_HIP(hipMemcpyAsync(B->ctrl_h, B->ctrl, (size_t)S * sizeof(gmm::Ctrl), hipMemcpyDeviceToHost, P->stream));
     if (B->spec_dirty) {
       GMM_HIP(hipMemcpyAsync(B->spec_h, B->spec, (size_t)S * 4 * B->nblk * sizeof(double), hipMemcpyDeviceToHost,
                              P->stream));
@@ -1965,10 +1969,13 @@ int batch_create(gmm_batch* out, gmm_plan_s* P, int slots, int M) {
   if (hipHostMalloc((void**)&B->rows_h, (size_t)cap * sizeof(gmm::BatchRow), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&B->slots_h, (size_t)2 * slots * sizeof(gmm::BatchSlot), hipHostMallocDefault) !=
           hipSuccess ||
-      hipHostMalloc((void**)&B->ctrl_h, (size_t)slots * sizeof(gmm::Ctrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&B->ctrl_h, (size_t)slots * sizeof(gmm::Ctrl),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostMalloc((void**)&B->spec_h, (size_t)slots * 4 * B->nblk * sizeof(double), hipHostMallocDefault) !=
           hipSuccess)
     return bail(fail(GMM_ERR_NOMEM, "pinned host allocation failed"));
+  if (hipHostGetDevicePointer((void**)&B->ctrl_h_dev, B->ctrl_h, 0) != hipSuccess)
+    return bail(fail(GMM_ERR_HIP, "hipHostGetDevicePointer of the control blocks failed"));
   B->slot.assign(slots, BatchSlotState{});
   *out = B;
   return GMM_OK;

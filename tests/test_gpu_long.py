@@ -1,0 +1,60 @@
+"""The metric workload (15 modes, Nt = 2^14, Kerr + Raman + shock, M = 10) over
+0.1 m: 1 095 large steps, long enough for errors that recur in every large step
+to add up.  The single-precision plans are compared with the FP64 plan (tol
+1e-12; its first 2 mm match the oracle to 1.4e-14, test_gpu_metric), all in
+tolerance mode at tol 1e-7, where the stopping rule's own error is small.
+
+Two such recurring errors are guarded here:
+- the phase factor exp(D M dz) that carries the field from one large step to the
+  next, which single-precision plans keep in FP64: an FP32 factor puts a fixed
+  phase error of about 1e-7 rad on each bin, applied 1 095 times;
+- the BF16X3 rank factors U and V, kept in three bf16 planes: with two, each
+  entry keeps a residual of up to 2^-18 that is the same in every evaluation.
+Measured at 0.1 m: FP32 8.9e-6 and BF16X3 9.2e-6 from FP64; the photon
+number changes by 5e-7 in all three precisions (the FP64 run's 5.6e-7 is the
+trapezoid's truncation).  With U in two planes BF16X3 is 6.3e-5 from FP64 (and
+9e-4 at 1 m); an FP32 closing factor gave 1.6e-3 at 1 m.  The bounds below
+(2e-5, and 2e-6 on the photon number) catch both.
+"""
+import numpy as np
+import pytest
+
+from paper_1708_05324_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+L = 0.1
+TOL = 1e-7
+
+
+@pytest.fixture(scope="module")
+def runs():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_05324_amd import gmmpa
+    gmmpa.load_library()
+    w = synth.config3()
+    out = {}
+    for prec, tol in (("fp64", 1e-12), ("fp32", TOL), ("bf16x3", TOL)):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
+        dtype = torch.complex128 if prec == "fp64" else torch.complex64
+        res = plan.propagate(torch.from_numpy(w.A0).to(device="cuda", dtype=dtype), L, w.dz, w.M)
+        st = res.stats
+        out[prec] = (res.field.cpu().numpy().astype(np.complex128), st)
+        plan.close()
+        print(f"[{prec} tol {tol:g} L {L} m] {st['large_steps']} large steps, {st['iterations']} iterations, "
+              f"photon-number change {st['photons_out'] / st['photons_in'] - 1.0:.3e}", flush=True)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_long_propagation_matches_fp64(runs, prec):
+    ref, _ = runs["fp64"]
+    got, st = runs[prec]
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    drift = st["photons_out"] / st["photons_in"] - 1.0
+    print(f"[{prec}] field error vs FP64 at {L} m: {err:.3e}, photon-number change {drift:.3e}", flush=True)
+    assert st["nonconverged_steps"] == 0
+    assert err < 2e-5
+    assert abs(drift) < 2e-6
