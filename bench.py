@@ -31,7 +31,7 @@ PEAKS = {  # MI355X published dense peaks
     "mfma_bf16_TFLOPs": 2500.0,
     # three bf16 products per useful multiply-add: useful-work peak of the split contraction
     "mfma_bf16x3_TFLOPs": 2500.0 / 3.0,
-    # four on the rank-r route's contraction and projection (a third plane of the fixed factor)
+    # four on the packed and rank-r routes' contraction and projection (a third plane of the fixed matrix)
     "mfma_bf16x4_TFLOPs": 2500.0 / 4.0,
     # vector ALU with packed FP32 disabled: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
     "alu_fp32_TFLOPs": 78.6,
@@ -48,7 +48,8 @@ def work_per_eval(kind: str, N: int, Nt: int, prec: str, rank: int = 0, route: s
     rank > 0: the plan contracts through the factor S^ = U V (U: Np x r), so the
     Raman convolution acts on r rows and the products are 2 r Np Nt each.
     bf16x3 executes three bf16 products per useful multiply-add (four in the
-    rank-r contraction and projection, whose fixed factor has a third plane);
+    packed and rank-r contraction and projection, whose fixed matrix has a
+    third plane);
     the useful count is what is reported (against the matching useful-work peak).  The
     sub-step transforms and the spectral output also read the phase table
     (one complex per element)."""
@@ -276,7 +277,8 @@ def roofline(prof: dict, stats: dict, N: int, Nt: int, prec: str, workload: str,
     wk = work_per_eval(kind, N, Nt, prec, rank, route)
     sec = total_ms * 1e-3
     if wk["compute"] == "mfma":
-        split = "mfma_bf16x4_TFLOPs" if rank and kind in ("contract", "project") else "mfma_bf16x3_TFLOPs"
+        split = ("mfma_bf16x4_TFLOPs" if route != "general" and kind in ("contract", "project")
+                 else "mfma_bf16x3_TFLOPs")
         cpeak = PEAKS["mfma_fp64_TFLOPs" if prec == "fp64" else split if prec == "bf16x3" else "mfma_fp32_TFLOPs"]
     else:
         cpeak = PEAKS["alu_fp64_TFLOPs" if prec == "fp64" else "alu_fp32_TFLOPs"]

@@ -52,9 +52,10 @@ typedef enum {
   GMM_FP32 = 1,   /* complex64 fields, FP32 transforms, FP32 MFMA contraction */
   GMM_BF16X3 = 2  /* complex64 fields, FP32 transforms; contraction as S^hi B^hi + S^hi B^lo + S^lo B^hi
                      with bf16 hi/lo splits on MFMA, FP32 accumulation (packed, rank-r and general routes up
-                     to 15 modes; the wide rank-r route up to 55).  On the rank-r route the fixed factors
-                     U and V carry a third plane lo2 and a fourth product S^lo2 B^hi, so that no fixed
-                     rounding of the coupling repeats in every evaluation.  Single-precision plans keep
+                     to 15 modes; the wide rank-r route up to 55).  On the packed and rank-r routes the
+                     fixed matrices (S^, or its factors U and V) carry a third plane lo2 and a fourth
+                     product S^lo2 B^hi, so that no fixed rounding of the coupling repeats in every
+                     evaluation.  Single-precision plans keep
                      the phase factor that ends each large step in FP64. */
 } gmm_precision;
 /* With Raman and Nt >= 2^13, the Raman convolution drops the samples of h_R

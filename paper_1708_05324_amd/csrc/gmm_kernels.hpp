@@ -593,8 +593,9 @@ __global__ __launch_bounds__(256) void k_contract_reg(
   }
 }
 
-// BF16 split contraction C = S^hi B'hi + S^hi B'lo + S^lo B'hi (FP32 accumulate)
-// on v_mfma_f32_16x16x32_bf16, for Rpad <= 128.  Lane l supplies
+// BF16 split contraction C = S^hi B'hi + S^hi B'lo + S^lo B'hi + S^lo2 B'hi (FP32
+// accumulate) on v_mfma_f32_16x16x32_bf16, for Rpad <= 128.  The fixed matrix S^
+// has a third plane lo2, so that no rounding of it recurs in every evaluation.  Lane l supplies
 // A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and holds
 // D[4 (l / 16) + i][l % 16] in accumulator register i (measured with a probe).
 // The coupling slices (hi, lo) stay in registers; each 64-column tile of B'
@@ -635,16 +636,18 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   for (int i = tid; i < N * N; i += 256) sP[i] = pidx[i];
-  // coupling operands: row = 16 RT wave + 16 r + lr, k = 32 s + 8 lk .. + 7  (rows of KPAD bf16 = KB chunks)
-  bf16x8 ah[RT][KS], al[RT][KS];
+  // coupling operands: row = 16 RT wave + 16 r + lr, k = 32 s + 8 lk .. + 7  (rows of KPAD bf16 = KB chunks);
+  // Slo holds the lo plane, then the lo2 plane
+  bf16x8 ah[RT][KS], al[RT][KS], al2[RT][KS];
 #pragma unroll
   for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const size_t idx = (size_t)(wave * 16 * RT + r * 16 + lr) * KB + 4 * s + lk;
-      uint4 h = Shi[idx], l = Slo[idx];
+      uint4 h = Shi[idx], l = Slo[idx], l2 = Slo[(size_t)RPAD * KB + idx];
       ah[r][s] = __builtin_bit_cast(bf16x8, h);
       al[r][s] = __builtin_bit_cast(bf16x8, l);
+      al2[r][s] = __builtin_bit_cast(bf16x8, l2);
     }
   const int tiles_per_j = Nt / TN;
   // chunk c of a tile: plane = c / (KB TN), kb = (c / TN) % KB, t = c % TN
@@ -687,6 +690,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16(
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r][s], bh, acc[r][c], 0, 0, 0);
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r][s], bl, acc[r][c], 0, 0, 0);
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r][s], bh, acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2[r][s], bh, acc[r][c], 0, 0, 0);
         }
       }
     }

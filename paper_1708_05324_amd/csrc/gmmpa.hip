@@ -156,7 +156,7 @@ struct gmm_plan_s {
   void* Hs = nullptr;      // [nt] ((1 - fR) + fR H / H0) / nt (blended Raman filter)
   void* ST = nullptr;      // [rpad][rpad] packed coupling matrix, transposed (FP64 / FP32)
   void* Shi = nullptr;     // [rpad][128] bf16 high part of the packed matrix, K contiguous (BF16X3)
-  void* Slo = nullptr;     // [rpad][128] bf16 low part
+  void* Slo = nullptr;     // [2][rpad][128] bf16 lo and lo2 planes
   // rank-r route (Raman on, low-rank packed matrix): S^ = U V
   bool factored = false;
   int rank = 0, rq = 0, kp = 0;  // r, r rounded up to 16, Np rounded up to 64
@@ -1091,17 +1091,24 @@ float host_bf16_value(uint16_t h) {
   std::memcpy(&x, &u, 4);
   return x;
 }
+// A fixed operand in three bf16 planes: v = hi + lo + lo2 to about 2^-26 of v (two planes leave up to 2^-18,
+// the same in every evaluation).
+void host_bf16_split3(double v, uint16_t* h, uint16_t* l, uint16_t* l2) {
+  *h = host_bf16((float)v);
+  const double r1 = v - (double)host_bf16_value(*h);
+  *l = host_bf16((float)r1);
+  *l2 = host_bf16((float)(r1 - (double)host_bf16_value(*l)));
+}
 
 // hi/lo split of the packed coupling matrix, rows (p,l) with K = 128 contiguous.
 int upload_bf16_split(gmm_plan_s* P, const std::vector<double>& ST) {
   const int K = gmm::kBf16Kpad;
-  std::vector<uint16_t> hi((size_t)P->rpad * K, 0), lo((size_t)P->rpad * K, 0);
+  const size_t n = (size_t)P->rpad * K;
+  std::vector<uint16_t> hi(n, 0), lo(2 * n, 0);  // lo: the lo plane, then the lo2 plane
   for (int r = 0; r < P->rpad; ++r)
     for (int k = 0; k < P->Np; ++k) {
-      const float x = (float)ST[(size_t)k * P->rpad + r];
-      const uint16_t h = host_bf16(x);
-      hi[(size_t)r * K + k] = h;
-      lo[(size_t)r * K + k] = host_bf16(x - host_bf16_value(h));
+      const size_t o = (size_t)r * K + k;
+      host_bf16_split3(ST[(size_t)k * P->rpad + r], &hi[o], &lo[o], &lo[n + o]);
     }
   int rc;
   if ((rc = dev_alloc(&P->const_bytes, &P->Shi, hi.size() * 2)) || (rc = dev_alloc(&P->const_bytes, &P->Slo, lo.size() * 2)))
@@ -1171,14 +1178,8 @@ int try_factor(gmm_plan_s* P, const double* SK, const std::vector<int2>& pairs, 
   GMM_HIP(hipMemcpy(P->VT, vt.data(), vt.size() * sizeof(T), hipMemcpyHostToDevice));
   GMM_HIP(hipMemcpy(P->UT, ut.data(), ut.size() * sizeof(T), hipMemcpyHostToDevice));
   if (P->bf16) {
-    // fixed factors in three bf16 planes: x = hi + lo + lo2 to about 2^-26 of x (two planes leave up to 2^-18,
-    // the same in every evaluation)
-    auto split3 = [](double v, uint16_t* h, uint16_t* l, uint16_t* l2) {
-      *h = host_bf16((float)v);
-      const double r1 = v - (double)host_bf16_value(*h);
-      *l = host_bf16((float)r1);
-      *l2 = host_bf16((float)(r1 - (double)host_bf16_value(*l)));
-    };
+    // fixed factors in three bf16 planes
+    const auto split3 = host_bf16_split3;
     const size_t un = (size_t)P->rpad * 64;
     std::vector<uint16_t> hi(un, 0), lo(2 * un, 0);
     for (int row = 0; row < Np; ++row)
