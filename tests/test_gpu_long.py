@@ -14,7 +14,10 @@ Measured at 0.1 m: FP32 8.9e-6 and BF16X3 9.2e-6 from FP64; the photon
 number changes by 5e-7 in all three precisions (the FP64 run's 5.6e-7 is the
 trapezoid's truncation).  With U in two planes BF16X3 is 6.3e-5 from FP64 (and
 9e-4 at 1 m); an FP32 closing factor gave 1.6e-3 at 1 m.  The bounds below
-(2e-5, and 2e-6 on the photon number) catch both.
+(2e-5, and 2e-6 on the photon number) catch both.  The packed route (the
+route of a full-rank tensor, factor_policy 1) keeps its matrix S^ in three
+planes too: BF16X3 8.6e-6 and FP32 9.1e-6 from FP64 at 0.1 m, against 3.9e-5
+with S^ in two planes.
 """
 import numpy as np
 import pytest
@@ -36,25 +39,30 @@ def runs():
     gmmpa.load_library()
     w = synth.config3()
     out = {}
-    for prec, tol in (("fp64", 1e-12), ("fp32", TOL), ("bf16x3", TOL)):
-        plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30)
+    for prec, tol, policy in (("fp64", 1e-12, 0), ("fp32", TOL, 0), ("bf16x3", TOL, 0), ("fp32", TOL, 1),
+                              ("bf16x3", TOL, 1)):
+        plan = gmmpa.plan_from_workload(w, precision=prec, tol=tol, max_iter=30, factor_policy=policy)
         dtype = torch.complex128 if prec == "fp64" else torch.complex64
         res = plan.propagate(torch.from_numpy(w.A0).to(device="cuda", dtype=dtype), L, w.dz, w.M)
         st = res.stats
-        out[prec] = (res.field.cpu().numpy().astype(np.complex128), st)
+        out[(prec, policy)] = (res.field.cpu().numpy().astype(np.complex128), st, plan.rank())
         plan.close()
-        print(f"[{prec} tol {tol:g} L {L} m] {st['large_steps']} large steps, {st['iterations']} iterations, "
-              f"photon-number change {st['photons_out'] / st['photons_in'] - 1.0:.3e}", flush=True)
+        print(f"[{prec} policy {policy} tol {tol:g} L {L} m] {st['large_steps']} large steps, "
+              f"{st['iterations']} iterations, photon-number change "
+              f"{st['photons_out'] / st['photons_in'] - 1.0:.3e}", flush=True)
     return out
 
 
+@pytest.mark.parametrize("policy", [0, 1], ids=["rank45", "packed"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_long_propagation_matches_fp64(runs, prec):
-    ref, _ = runs["fp64"]
-    got, st = runs[prec]
+def test_long_propagation_matches_fp64(runs, prec, policy):
+    ref, _, _ = runs[("fp64", 0)]
+    got, st, rank = runs[(prec, policy)]
+    assert rank == (45 if policy == 0 else 0)  # the route the case names
     err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     drift = st["photons_out"] / st["photons_in"] - 1.0
-    print(f"[{prec}] field error vs FP64 at {L} m: {err:.3e}, photon-number change {drift:.3e}", flush=True)
+    print(f"[{prec} policy {policy}] field error vs FP64 at {L} m: {err:.3e}, photon-number change {drift:.3e}",
+          flush=True)
     assert st["nonconverged_steps"] == 0
     assert err < 2e-5
     assert abs(drift) < 2e-6
