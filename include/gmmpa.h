@@ -73,7 +73,11 @@ typedef struct {
   double fR;            /* Raman fraction, 0 <= fR <= 1 */
   int self_steepening;  /* 1: keep (1 + (i/omega0) d/dt); 0: replace it by 1 */
   int precision;        /* gmm_precision */
-  double tol;           /* threshold on ||psi^(n+1) - psi^(n)|| / ||psi^(n+1)|| (FP64) */
+  double tol;           /* threshold on ||psi^(n+1) - psi^(n)|| / ||psi^(n+1)|| (FP64).  The error a stopped
+                           iteration leaves keeps its sign from one large step to the next, so it adds up
+                           along the fibre: over 1 m of the 15-mode GRIN workload (11 000 large steps) the
+                           field is within 9.6e-4 of FP64 at tol 1e-5, 1.5e-4 at 1e-6 and 2.5e-5 at 1e-7
+                           (FP32 and GMM_BF16X3 alike) */
   int max_iter;         /* iteration cap per large step (>= 1) */
   int fixed_iters;      /* > 0: run exactly this many iterations per large step, ignore tol */
   int factor_policy;    /* contraction route.  0 (auto): a real S^K = S^R with S_plmn = S_plnm = S_lpmn
