@@ -1524,23 +1524,36 @@ __device__ __forceinline__ void trapz_block(const cplx<T>* __restrict__ psi0, co
 //   Nl  : the iteration's spectral outputs: first = 1: rows 0..M (row 0 is I_0);
 //         else rows 1..M of the sub-steps j = 1..M at I + (j - 1) nn, and I_0 kept
 //   psi : [M][N][Nt] stored iterates exp(D z_j) psi_j, row j - 1 = sub-step j
+//   psi0: the field at the start of the large step: a kept copy, or, on the first
+//         iteration, the previous step's last iterate itself (a row of psi: no
+//         close launch copies it), which then goes to psi0_keep; `reset`, if not
+//         NULL, is the control block to clear for the new large step
 //   Em64: NULL, or exp(D_w M dz) in FP64 for a single-precision field: the factor
 //         that carries the field from one large step to the next (the others
 //         only shape a step's iterates).  A rounded phase there repeats every
 //         step and adds up over a long fiber (about 1e-7 rad per bin and step),
 //         so the last sub-step takes the FP64 factor and product, rounded once.
 template <typename T>
-__device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0,
-                                                const cplx<T>* __restrict__ I, cplx<T>* __restrict__ psi,
+__device__ __forceinline__ void trapz_lab_block(const cplx<T>* psi0, const cplx<T>* __restrict__ I0,
+                                                const cplx<T>* __restrict__ I, cplx<T>* psi,
                                                 cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
                                                 const cplx<double>* __restrict__ Em64, int first, int M, long nn,
-                                                T dz, double* __restrict__ partials) {
+                                                T dz, double* __restrict__ partials,
+                                                cplx<T>* __restrict__ psi0_keep = nullptr, Ctrl* reset = nullptr) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   double d = 0.0, s = 0.0;
+  if (reset != nullptr && e == 0) {
+    reset->eps = 0.0;
+    reset->iters = 0;
+    reset->done = 0;
+    reset->status = 0;
+    reset->pad = 0;
+  }
   if (e < nn) {
-    const cplx<T> p0 = psi0[e];
+    const cplx<T> p0 = psi0[e];  // psi0 may be a row of psi: read before any row is written
     const cplx<T> i0 = I0[e];
     if (first) I0_keep[e] = i0;
+    if (psi0_keep != nullptr) psi0_keep[e] = p0;
     const cplx<T> h0 = cscale(i0, T(0.5));
     cplx<T> run = {0, 0};
     const cplx<double> e64 = Em64 != nullptr ? Em64[e] : cplx<double>{0.0, 1.0};
@@ -1586,12 +1599,12 @@ __device__ __forceinline__ void trapz_lab_block(const cplx<T>* __restrict__ psi0
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_trapz_lab(
-    const cplx<T>* __restrict__ psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I,
-    cplx<T>* __restrict__ psi, cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E,
-    const cplx<double>* __restrict__ Em64, int first, int M, long nn, T dz, double* __restrict__ partials,
-    const Ctrl* ctrl) {
+    const cplx<T>* psi0, const cplx<T>* __restrict__ I0, const cplx<T>* __restrict__ I, cplx<T>* psi,
+    cplx<T>* __restrict__ I0_keep, const cplx<T>* __restrict__ E, const cplx<double>* __restrict__ Em64, int first,
+    int M, long nn, T dz, double* __restrict__ partials, const Ctrl* ctrl, cplx<T>* __restrict__ psi0_keep,
+    Ctrl* reset) {
   if (skip_iteration(ctrl)) return;
-  trapz_lab_block<T>(psi0, I0, I, psi, I0_keep, E, Em64, first, M, nn, dz, partials);
+  trapz_lab_block<T>(psi0, I0, I, psi, I0_keep, E, Em64, first, M, nn, dz, partials, psi0_keep, reset);
 }
 
 template <typename T>

@@ -47,10 +47,13 @@ struct Launch {
                                  int j0, double domega, double gscale, double inv_omega0, int shock,
                                  const cplx<T>* tw, const Ctrl* ctrl, hipStream_t s);
   // E != nullptr: lab-frame iterates (the phase table [M + 1][N][Nt] is applied inside the trapezoid);
-  // Em64 != nullptr (with E): exp(D M dz) in FP64 for the sub-step that ends the large step
+  // Em64 != nullptr (with E): exp(D M dz) in FP64 for the sub-step that ends the large step;
+  // psi0_keep / reset (with E, first iteration): psi0 is the previous step's last iterate, copied to psi0_keep,
+  // and the control block `reset` is cleared for the new large step
   static hipError_t trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi, cplx<T>* I0_keep,
                           int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl, hipStream_t s,
-                          const cplx<T>* E = nullptr, const cplx<double>* Em64 = nullptr);
+                          const cplx<T>* E = nullptr, const cplx<double>* Em64 = nullptr,
+                          cplx<T>* psi0_keep = nullptr, Ctrl* reset = nullptr);
   // dst = Em .* src (Em = nullptr: a copy; Em64 != nullptr: the factor and product in FP64); with ctrl, also
   // resets the control block for the next large step
   static hipError_t close(const cplx<T>* src, cplx<T>* dst, const cplx<T>* Em, long nn, Ctrl* ctrl, hipStream_t s,

@@ -255,10 +255,13 @@ hipError_t Launch<T>::spectral_out(int logn, const cplx<T>* in, cplx<T>* out, co
 template <typename T>
 hipError_t Launch<T>::trapz(const cplx<T>* psi0, const cplx<T>* I0, const cplx<T>* I, cplx<T>* psi,
                             cplx<T>* I0_keep, int first, int M, long nn, T dz, double* partials, const Ctrl* ctrl,
-                            hipStream_t s, const cplx<T>* E, const cplx<double>* Em64) {
+                            hipStream_t s, const cplx<T>* E, const cplx<double>* Em64, cplx<T>* psi0_keep,
+                            Ctrl* reset) {
   if (E != nullptr)
     hipLaunchKernelGGL((k_trapz_lab<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, E, Em64,
-                       first, M, nn, dz, partials, ctrl);
+                       first, M, nn, dz, partials, ctrl, psi0_keep, reset);
+  else if (psi0_keep != nullptr || reset != nullptr)
+    return hipErrorInvalidValue;  // the start field is a separate kept copy in the psi frame
   else
     hipLaunchKernelGGL((k_trapz<T>), dim3(trapz_blocks(nn)), dim3(256), 0, s, psi0, I0, I, psi, I0_keep, first, M,
                        nn, dz, partials, ctrl);

@@ -375,6 +375,9 @@ std::vector<ContractCand> contraction_candidates(const gmm_plan_s* P) {
 template <typename T>
 struct Runner {
   gmm_plan_s* P;
+  // field at the start of the current large step: psi0, or (lab frame, after the first large step) the previous
+  // step's last iterate, a row of psi, which the step's first trapezoid copies to psi0
+  const cplx<T>* start = nullptr;
   const cplx<T>* tw() const { return (const cplx<T>*)P->tw; }
 
   // The route-specific middle of one evaluation over `count` field rows of
@@ -596,15 +599,23 @@ struct Runner {
   int iteration(int m, double dz, bool first, int part = 0) {
     const long nn = (long)P->N * P->nt;
     cplx<T>* W = (cplx<T>*)P->work;
-    int rc = first ? eval((const cplx<T>*)P->psi0, 0, m + 1, 0, dz, W, P->ctrl, part)
-                   : eval((const cplx<T>*)P->psi, P->N, m, 1, dz, W, P->ctrl, part);
+    const cplx<T>* psi0 = (const cplx<T>*)P->psi0;
+    const cplx<T>* src0 = start != nullptr ? start : psi0;
+    // The first iteration of a large step that starts from the previous step's last iterate: the control block
+    // still says that step is done, so these launches test no stop flag, and the trapezoid clears the block
+    // (before the norm reads it) and keeps the start field in psi0 for the later iterations.
+    const bool fresh = first && src0 != psi0;
+    const Ctrl* c = fresh ? nullptr : P->ctrl;
+    int rc = first ? eval(src0, 0, m + 1, 0, dz, W, c, part)
+                   : eval((const cplx<T>*)P->psi, P->N, m, 1, dz, W, c, part);
     if (rc || part == 1) return rc;
     const cplx<T>* I0 = first ? W : (const cplx<T>*)P->I0;
     const cplx<T>* I = first ? W + nn : W;
-    GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz((const cplx<T>*)P->psi0, I0, I, (cplx<T>*)P->psi,
-                                                   (cplx<T>*)P->I0, first ? 1 : 0, m, nn, (T)dz, P->partials, P->ctrl,
-                                                   P->stream, lab_frame(P) ? (const cplx<T>*)P->E : nullptr,
-                                                   lab_frame(P) ? last_factor(m) : nullptr));
+    GMM_LAUNCH(P, GMM_PROF_TRAPZ, Launch<T>::trapz(first ? src0 : psi0, I0, I, (cplx<T>*)P->psi, (cplx<T>*)P->I0,
+                                                   first ? 1 : 0, m, nn, (T)dz, P->partials, c, P->stream,
+                                                   lab_frame(P) ? (const cplx<T>*)P->E : nullptr,
+                                                   lab_frame(P) ? last_factor(m) : nullptr,
+                                                   fresh ? (cplx<T>*)P->psi0 : nullptr, fresh ? P->ctrl : nullptr));
     GMM_LAUNCH(P, GMM_PROF_NORM, gmm::launch_norm_final(P->partials, gmm::trapz_blocks(nn), P->ctrl, P->prm.tol,
                                                         P->prm.fixed_iters, P->prm.max_iter, P->stream,
                                                         P->h_ctrl_dev));
@@ -700,7 +711,9 @@ struct Runner {
                                   nullptr, 0, P->N, P->nt, 1, nullptr, P->stream));
     long done = 0;
     int status = GMM_OK;
-    GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));  // later large steps: reset by the close launch
+    GMM_HIP(gmm::launch_ctrl_reset(P->ctrl, P->stream));  // later large steps: by the close, or (lab frame) by
+                                                           // the step's first trapezoid
+    start = (const cplx<T>*)P->psi0;
     while (done < n_small) {
       const int m = (int)std::min<long>(M, n_small - done);
       int n_enq = 0;
@@ -746,21 +759,28 @@ struct Runner {
       s.evaluations += 1 + (long long)c.iters * m;
       if (c.iters > s.max_iters_seen) s.max_iters_seen = c.iters;
       s.last_eps = c.eps;
-      // A~(z0 + m dz) = exp(D m dz) psi_m (coupled operator: exp(i lam m dz) psi_m in the eigenbasis, which is
-      // also the next large step's psi(z0) there)
-      GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn, (cplx<T>*)P->psi0,
-                                                   lab_frame(P) ? nullptr : (const cplx<T>*)P->E + (size_t)m * nn, nn,
-                                                   P->ctrl, P->stream, lab_frame(P) ? nullptr : last_factor(m)));
+      // A~(z0 + m dz) = exp(D m dz) psi_m.  Lab-frame iterates already carry the factor: the last one is the
+      // next large step's start field as it stands (no close launch; see iteration()).  Otherwise the close
+      // applies the factor into psi0 (coupled operator: exp(i lam m dz) psi_m in the eigenbasis, which is also
+      // the next large step's psi(z0) there) and resets the control block.
+      if (lab_frame(P))
+        start = (const cplx<T>*)P->psi + (size_t)(m - 1) * nn;
+      else
+        GMM_LAUNCH(P, GMM_PROF_CLOSE, Launch<T>::close((const cplx<T>*)P->psi + (size_t)(m - 1) * nn,
+                                                     (cplx<T>*)P->psi0, (const cplx<T>*)P->E + (size_t)m * nn, nn,
+                                                     P->ctrl, P->stream, last_factor(m)));
       s.large_steps++;
       s.small_steps += m;
       done += m;
       P->prof.cur_step++;
     }
+    const cplx<T>* fin = start != nullptr ? start : (const cplx<T>*)P->psi0;  // the field at L
+    start = nullptr;
     if (P->cpl_exact)  // back to the modes
       GMM_HIP(Launch<T>::mode_mix(false, (const cplx<T>*)P->psi0, P->N, (cplx<T>*)P->psi0, (const cplx<T>*)P->Uc,
                                   nullptr, 0, P->N, P->nt, 1, nullptr, P->stream));
-    if ((rc = spec_sums((const cplx<T>*)P->psi0, &s.energy_out, &s.photons_out))) return rc;
-    GMM_HIP(Launch<T>::fft_rows(P->logn, -1, (const cplx<T>*)P->psi0, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
+    if ((rc = spec_sums(fin, &s.energy_out, &s.photons_out))) return rc;
+    GMM_HIP(Launch<T>::fft_rows(P->logn, -1, fin, (cplx<T>*)Aout, (T)1, P->N, tw(), P->stream));
     GMM_HIP(hipStreamSynchronize(P->stream));
     if (P->prof.on) P->prof.collect();
     if (st) *st = s;
