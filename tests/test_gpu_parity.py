@@ -103,7 +103,9 @@ def test_linear_propagation_is_exact(torch_gpu, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("M,nsteps", [(5, 15), (4, 10)])   # 10 = 2 x 4 + a last large step of 2
+# 10 = 2 x 4 + a last large step of 2; 5 = 2 x 2 + a last large step of 1; M = 1: every large step is one sub-step
+# (each large step starts from row 0 of the previous step's iterates)
+@pytest.mark.parametrize("M,nsteps", [(5, 15), (4, 10), (2, 5), (1, 6)])
 def test_propagation_fixed_iterations_matches_oracle(torch_gpu, prec, M, nsteps):
     torch = torch_gpu
     w = small_workload(N_groups=2, nt=256, fR=0.18, s=1)
