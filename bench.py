@@ -100,19 +100,23 @@ def read_traffic(kind: str, workload: str, prec: str):
 
 
 def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile: bool, make_plan=None,
-            repeats: int = 5):
+            repeats: int = 5, chain: bool = True):
     """Time `repeats` windows of `steps` large steps each (no per-kernel events
     inside them) and report the median window.  With `profile`, the warm-up
     times every kernel kind (per-kernel breakdown), and one more window of
     `steps` large steps after the timed ones brackets each launch of the
-    dominant kind with HIP events on the plan's stream (roofline)."""
+    dominant kind with HIP events on the plan's stream (roofline).  chain: each
+    propagation starts from the previous one's output (else from the launch
+    field, for workloads whose field grows without bound, like a random complex
+    coupling tensor)."""
     import torch
     from paper_1708_05324_amd import gmmpa
     plan = (make_plan(prec) if make_plan else
             gmmpa.plan_from_workload(w, precision=prec, tol=TOL[prec], max_iter=30))
     rank = plan.rank()
     dtype = torch.complex128 if prec == "fp64" else torch.complex64
-    A = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
+    A0 = torch.from_numpy(w.A0).to(device="cuda", dtype=dtype)
+    A = A0
     Ls = w.M * w.dz
     breakdown, dominant = None, None
     if warmup > 0:                    # first large step: code loading, allocation, cold caches
@@ -120,7 +124,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     if warmup > 1:                    # rest of the warm-up with every kernel kind timed: per-kernel breakdown
         if profile:
             plan.profile(True)
-        wres = plan.propagate(A, (warmup - 1) * Ls, w.dz, w.M)
+        wres = plan.propagate(A if chain else A0, (warmup - 1) * Ls, w.dz, w.M)
         A = wres.field
         if profile:
             breakdown = {k: (v[0] / wres.stats["large_steps"], v[1]) for k, v in plan.profile_read().items()}
@@ -130,7 +134,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
     for _ in range(max(1, repeats)):  # timed windows: only propagate between the two synchronisations
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = plan.propagate(A, steps * Ls, w.dz, w.M)
+        res = plan.propagate(A if chain else A0, steps * Ls, w.dz, w.M)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         A = res.field
@@ -143,7 +147,7 @@ def run_gpu(prec: str, w, steps: int, warmup: int, latency_solves: int, profile:
         plan.profile([dominant])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pres = plan.propagate(A, steps * Ls, w.dz, w.M)
+        pres = plan.propagate(A if chain else A0, steps * Ls, w.dz, w.M)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         prof = {dominant: plan.profile_read()[dominant]}
@@ -709,7 +713,9 @@ def main():
         def make(p):
             return gmmpa.Plan(w.betas, SK, w.hR, nt=w.nt, dt=w.dt, omega0=w.omega0, n2=w.n2, fR=w.fR,
                               self_steepening=w.self_steepening, precision=p, SR=SR, fixed_iters=3)
-        r = run_gpu(prec, w, max(4, args.steps // 4), max(2, args.warmup), 0, not args.no_profile, make)
+        # the random complex tensor is not conservative: the field grows along the fibre and becomes non-finite
+        # within about 12 large steps (in FP64 too), so every timed run is 5 large steps from the launch field
+        r = run_gpu(prec, w, 5, max(2, args.warmup), 0, not args.no_profile, make, chain=False)
         out = {"metric": "MPA steps/s, general-tensor route (complex S^K != S^R)", "unit": "small steps/s",
                "value": round(r["small_steps_per_s"], 2), "dtype": DTYPE[prec],
                "config": {"workload": "grin15_raman_nt16384_general_tensor", "n_modes": w.n_modes, "nt": w.nt,
